@@ -1,0 +1,414 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types an oracle formula: each checks a closed form, a special case, an
+invariant, an independent geometric construction or brute force on tiny inputs, chosen so
+that a dropped term, a wrong sign, a wrong index or a transposed operand in the oracle
+fails at least one of them. The paper prints no worked numerical example.
+"""
+
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import hsgd_oracle as O
+from paper_2307_03017_amd import scenes
+
+RNG = np.random.default_rng
+
+
+def _shift_maps(N, D, sx, sy):
+    """Per (view, plane) pure-translation maps view pixel -> reference pixel."""
+    G = np.zeros((N, D, 3, 3))
+    G[:, :] = np.eye(3)
+    G[..., 0, 2] = sx
+    G[..., 1, 2] = sy
+    return G
+
+
+def _rot(ax, ay, az):
+    cx, sx, cy, sy, cz, sz = np.cos(ax), np.sin(ax), np.cos(ay), np.sin(ay), np.cos(az), np.sin(az)
+    Rx = np.array([[1, 0, 0], [0, cx, -sx], [0, sx, cx]])
+    Ry = np.array([[cy, 0, sy], [0, 1, 0], [-sy, 0, cy]])
+    Rz = np.array([[cz, -sz, 0], [sz, cz, 0], [0, 0, 1]])
+    return Rz @ Ry @ Rx
+
+
+# ------------------------------------------------------------------ over operator (Eq. over)
+def test_single_opaque_plane_reproduces_its_colour():
+    # (a): alpha = 1 on one plane, planes in front transparent -> that plane's colour,
+    # whatever lies behind it, wherever all 4 taps are inside the plane.
+    rng = RNG(0)
+    D, H, W = 5, 9, 11
+    M = rng.uniform(size=(D, H, W, 4))
+    z0 = 2
+    M[:z0, ..., 3] = 0.0
+    M[z0, ..., 3] = 1.0
+    M[z0, ..., :3] = np.array([0.2, 0.7, 0.4])
+    G = _shift_maps(1, D, 1.3, -0.6)
+    C = O.render(M, G)[0]
+    inner = C[1:H - 1, 0:W - 3]      # taps x+1..x+2 and y-1..y stay inside
+    np.testing.assert_allclose(inner, np.broadcast_to([0.2, 0.7, 0.4], inner.shape), atol=1e-15)
+
+
+def test_transparent_planes_render_black():
+    # (b)
+    rng = RNG(1)
+    M = rng.uniform(size=(4, 6, 7, 4))
+    M[..., 3] = 0.0
+    G = _shift_maps(2, 4, 0.4, 0.25)
+    assert np.all(O.render(M, G) == 0.0)
+
+
+def test_two_planes_closed_form():
+    # front plane z=0, back plane z=1: C = c0 a0 + c1 a1 (1 - a0)   (identity warp)
+    rng = RNG(2)
+    M = rng.uniform(size=(2, 3, 4, 4))
+    G = _shift_maps(1, 2, 0.0, 0.0)
+    C = O.render(M, G)[0]
+    c0, a0, c1, a1 = M[0, ..., :3], M[0, ..., 3:], M[1, ..., :3], M[1, ..., 3:]
+    np.testing.assert_allclose(C, c0 * a0 + c1 * a1 * (1 - a0), rtol=0, atol=1e-15)
+
+
+def test_over_operator_in_paper_index_order():
+    # Eq. over with the paper's own indexing d = 1..D, d = D the front plane, evaluated
+    # with explicit products per pixel (z = D - d).
+    rng = RNG(3)
+    D, H, W = 6, 2, 3
+    M = rng.uniform(size=(D, H, W, 4))
+    G = _shift_maps(1, D, 0.0, 0.0)
+    C = O.render(M, G)[0]
+    for y, x in itertools.product(range(H), range(W)):
+        acc = np.zeros(3)
+        for d in range(1, D + 1):
+            z = D - d
+            prod = 1.0
+            for i in range(d + 1, D + 1):
+                prod *= 1.0 - M[D - i, y, x, 3]
+            acc += M[z, y, x, :3] * M[z, y, x, 3] * prod
+        np.testing.assert_allclose(C[y, x], acc, rtol=1e-14, atol=1e-15)
+
+
+def test_compositing_weights_telescope():
+    # sum_z A_z = 1 - prod_z (1 - a_z): the weights of Eq. overA sum to the total opacity.
+    rng = RNG(4)
+    a = rng.uniform(size=(7, 5, 6)).astype(np.float32)
+    A = O.select_scores_f32(a).astype(np.float64)
+    total = 1.0 - np.prod(1.0 - a.astype(np.float64), axis=0)
+    np.testing.assert_allclose(A.sum(axis=0), total, atol=5e-7)
+    # and rendering a white MPI returns exactly that opacity in every channel
+    M = np.ones((7, 5, 6, 4))
+    M[..., 3] = a
+    C = O.render(M, _shift_maps(1, 7, 0.0, 0.0))[0]
+    np.testing.assert_allclose(C[..., 0], total, atol=1e-12)
+
+
+# ------------------------------------------------------------------ homography (Eq. homo)
+def test_identity_pose_gives_identity_maps_and_reproduces_planes():
+    # (c)
+    K = np.array([[50.0, 0, 15.5], [0, 50.0, 11.5], [0, 0, 1]])
+    depths = scenes.plane_depths(4)
+    G = O.view_to_ref_maps(K, K[None], np.eye(3)[None], np.zeros((1, 3)), depths)
+    np.testing.assert_allclose(G[0], np.broadcast_to(np.eye(3), G[0].shape), atol=1e-15)
+    rng = RNG(5)
+    M = rng.uniform(size=(4, 24, 32, 4))
+    for z in range(4):
+        np.testing.assert_array_equal(O.sample_bilinear(M[z], np.eye(3)), M[z])
+
+
+def test_same_pose_as_reference_is_identity():
+    rng = RNG(6)
+    K = np.array([[80.0, 0.0, 40.0], [0.0, 75.0, 30.0], [0, 0, 1]])
+    Rr = _rot(0.1, -0.2, 0.05)
+    tr = rng.normal(size=3)
+    H = O.plane_homography(K, K, Rr, tr, 3.7, R_r=Rr, t_r=tr)
+    np.testing.assert_allclose(H, np.eye(3), atol=1e-12)
+
+
+def test_pure_translation_is_a_shift_of_f_t_over_d():
+    f = 400.0
+    K = np.array([[f, 0, 255.5], [0, f, 191.5], [0, 0, 1]])
+    t = np.array([0.07, -0.03, 0.0])
+    for d in (1.0, 2.5, 100.0):
+        H = O.plane_homography(K, K, np.eye(3), t, d)
+        expect = np.eye(3)
+        expect[0, 2] = f * t[0] / d
+        expect[1, 2] = f * t[1] / d
+        np.testing.assert_allclose(H, expect, atol=1e-12)
+        G = O.view_to_ref_maps(K, K[None], np.eye(3)[None], t[None], np.array([d]))[0, 0]
+        np.testing.assert_allclose(G[:2, 2], -f * t[:2] / d, atol=1e-12)
+
+
+def test_homography_matches_explicit_ray_plane_geometry():
+    # Back-project a reference pixel onto the plane z_cam = d of the reference camera, move
+    # it to world and into source camera i, project: independent of Eq. homo's algebra.
+    rng = RNG(7)
+    Kr = np.array([[90.0, 0.0, 31.0], [0.0, 85.0, 22.0], [0, 0, 1]])
+    Ki = np.array([[70.0, 0.0, 28.0], [0.0, 72.0, 25.0], [0, 0, 1]])
+    Rr, Ri = _rot(0.05, 0.1, -0.02), _rot(-0.1, 0.04, 0.2)
+    tr, ti = rng.normal(size=3) * 0.3, rng.normal(size=3) * 0.3
+    for d in (1.5, 4.0, 20.0):
+        H = O.plane_homography(Kr, Ki, Ri, ti, d, R_r=Rr, t_r=tr)
+        for u, v in ((0.0, 0.0), (12.3, 40.1), (63.0, 5.5)):
+            Xr = d * np.linalg.solve(Kr, [u, v, 1.0])            # on the plane z = d
+            Xw = Rr.T @ (Xr - tr)                                 # x_cam = R x_w + t
+            Xi = Ri @ Xw + ti
+            p = Ki @ Xi
+            q = H @ np.array([u, v, 1.0])
+            np.testing.assert_allclose(q[:2] / q[2], p[:2] / p[2], rtol=1e-11, atol=1e-9)
+
+
+def test_level_intrinsics_follow_pixel_centres():
+    # A 3D point projects to pixel x at full resolution and to (x + 0.5) * s - 0.5 at a
+    # level resampled by s (pixel-index coordinates).
+    K = np.array([[400.0, 0.0, 255.5], [0.0, 400.0, 191.5], [0, 0, 1]])
+    Kl = O.level_intrinsics(K, 512, 384, 128, 96)
+    X = np.array([0.3, -0.2, 2.0])
+    p, pl = K @ X, Kl @ X
+    np.testing.assert_allclose(pl[:2] / pl[2], (p[:2] / p[2] + 0.5) * 0.25 - 0.5, atol=1e-12)
+
+
+# ------------------------------------------------------------------ warp (grid_sample)
+def test_integer_shift_is_an_exact_copy():
+    rng = RNG(8)
+    P = rng.uniform(size=(10, 12, 4))
+    G = np.eye(3)
+    G[0, 2], G[1, 2] = 3.0, -2.0
+    S = O.sample_bilinear(P, G)
+    expect = np.zeros_like(P)
+    expect[2:, :9] = P[:8, 3:]
+    np.testing.assert_array_equal(S, expect)
+
+
+def test_bilinear_reproduces_linear_fields():
+    # a x + b y + c is reproduced exactly wherever all taps lie inside: pins the weights
+    # (a swapped fx/fy or (1-f)/f fails it).
+    H, W = 20, 25
+    ys, xs = np.mgrid[0:H, 0:W].astype(float)
+    P = np.stack([0.3 * xs - 0.7 * ys + 2.0, 1.1 * xs + 0.2 * ys], axis=-1)
+    G = np.eye(3)
+    G[0, 2], G[1, 2] = 2.37, 1.61
+    S = O.sample_bilinear(P, G)
+    u, v = xs + 2.37, ys + 1.61
+    inside = (u <= W - 1) & (v <= H - 1)
+    expect = np.stack([0.3 * u - 0.7 * v + 2.0, 1.1 * u + 0.2 * v], axis=-1)
+    np.testing.assert_allclose(S[inside], expect[inside], atol=1e-12)
+
+
+def test_warp_adjoint_dot_product():
+    # <S v, u> = <v, S^T u> for a general (rotating, zooming) homography
+    rng = RNG(9)
+    H, W = 17, 23
+    K = np.array([[30.0, 0.0, 11.0], [0.0, 30.0, 8.0], [0, 0, 1]])
+    Hm = O.plane_homography(K, K, _rot(0.02, -0.03, 0.1), np.array([0.1, 0.05, 0.2]), 2.0)
+    G = np.linalg.inv(Hm)
+    v = rng.normal(size=(H, W, 4))
+    u = rng.normal(size=(H, W, 4))
+    lhs = np.sum(O.sample_bilinear(v, G) * u)
+    rhs = np.sum(v * O.sample_bilinear_T(u, G, H, W))
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1.0)
+
+
+# ------------------------------------------------------------------ gradient
+def _tiny_problem(seed, general=False, D=5, H=9, W=10, N=3):
+    rng = RNG(seed)
+    M = rng.uniform(0.05, 0.95, size=(D, H, W, 4))
+    I = rng.uniform(size=(N, H, W, 3))
+    if general:
+        K = np.array([[12.0, 0.0, (W - 1) / 2], [0.0, 12.0, (H - 1) / 2], [0, 0, 1]])
+        R = np.stack([_rot(*(rng.normal(size=3) * 0.05)) for _ in range(N)])
+        t = rng.normal(size=(N, 3)) * 0.1
+        G = O.view_to_ref_maps(K, np.repeat(K[None], N, 0), R, t, scenes.plane_depths(D))
+    else:
+        G = _shift_maps(N, D, 0.0, 0.0)
+        G[..., 0, 2] = rng.uniform(-2, 2, size=(N, D))
+        G[..., 1, 2] = rng.uniform(-2, 2, size=(N, D))
+    return M, I, G
+
+
+@pytest.mark.parametrize("general", [False, True])
+def test_gradient_matches_central_differences(general):
+    # (e): a single MPI scalar enters every ray affinely, so L is quadratic in it and the
+    # central difference is exact up to rounding.
+    M, I, G = _tiny_problem(10 + general, general=general)
+    _, g = O.loss_and_grad(M, G, I)
+    rng = RNG(20)
+    h = 1e-3
+    for _ in range(40):
+        idx = tuple(int(rng.integers(0, s)) for s in M.shape)
+        Mp, Mm = M.copy(), M.copy()
+        Mp[idx] += h
+        Mm[idx] -= h
+        fd = (O.photometric_loss(O.render(Mp, G), I) - O.photometric_loss(O.render(Mm, G), I)) / (2 * h)
+        assert abs(fd - g[idx]) <= 1e-9 * max(1.0, abs(g[idx])), (idx, fd, g[idx])
+
+
+def test_vjp_matches_directional_difference():
+    M, _, G = _tiny_problem(12)
+    rng = RNG(21)
+    gimg = rng.normal(size=(len(G),) + M.shape[1:3] + (3,))
+    V = rng.normal(size=M.shape)
+    h = 1e-4
+    fd = (np.sum(O.render(M + h * V, G) * gimg) - np.sum(O.render(M - h * V, G) * gimg)) / (2 * h)
+    an = np.sum(O.render_vjp(M, G, gimg) * V)
+    # <g, J V> is a polynomial of degree <= 2D in h; the O(h^2) term is tiny here
+    assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+def test_ground_truth_is_stationary():
+    M, _, G = _tiny_problem(13)
+    I = O.render(M, G)
+    L, g = O.loss_and_grad(M, G, I)
+    assert L == 0.0 and np.all(g == 0.0)
+
+
+def test_loss_value_closed_form():
+    # one view, one pixel, one opaque plane: L = |c - I|^2 / 2
+    M = np.zeros((1, 1, 1, 4))
+    M[0, 0, 0] = [0.2, 0.5, 0.9, 1.0]
+    I = np.array([[[[0.1, 0.1, 0.1]]]])
+    L, g = O.loss_and_grad(M, _shift_maps(1, 1, 0.0, 0.0), I)
+    assert abs(L - 0.5 * (0.01 + 0.16 + 0.64)) < 1e-15
+    # dL/dc = (c - I) * a * T;  dL/da = T <c - I, c - B> with B = 0
+    np.testing.assert_allclose(g[0, 0, 0, :3], [0.1, 0.4, 0.8], atol=1e-15)
+    assert abs(g[0, 0, 0, 3] - (0.1 * 0.2 + 0.4 * 0.5 + 0.8 * 0.9)) < 1e-15
+
+
+# ------------------------------------------------------------------ selection (Sec. 3.3)
+def _brute_select(A, k):
+    D = A.shape[0]
+    mask = np.zeros(A.shape, bool)
+    for idx in itertools.product(*[range(s) for s in A.shape[1:]]):
+        col = A[(slice(None),) + idx]
+        for z in range(D):
+            beaten = sum(1 for z2 in range(D)
+                         if col[z2] > col[z] or (col[z2] == col[z] and z2 < z))
+            mask[(z,) + idx] = beaten < k
+    return mask
+
+
+@pytest.mark.parametrize("D,k", [(6, 1), (6, 2), (8, 3), (8, 8), (5, 7)])
+def test_topk_against_brute_force(D, k):
+    rng = RNG(30 + D + k)
+    # quantised alphas produce exact ties in A (including all-zero columns)
+    a = rng.integers(0, 5, size=(D, 4, 5)).astype(np.float32) / 4
+    A = O.select_scores_f32(a)
+    mask = O.select_active(a, k)
+    np.testing.assert_array_equal(mask, _brute_select(A, min(k, D)))
+    assert np.all(mask.sum(axis=0) == min(k, D))
+
+
+def test_select_scores_follow_eq_gradient():
+    # A_z = a_z prod_{j<z}(1 - a_j), the paper's alpha gradient on the reference view
+    rng = RNG(31)
+    a = rng.uniform(size=(6, 3, 3))
+    A = O.select_scores_f32(a)
+    for z in range(6):
+        ref = a[z] * np.prod(1.0 - a[:z], axis=0)
+        np.testing.assert_allclose(A[z], ref, rtol=2e-6, atol=1e-7)
+
+
+def test_select_threshold_and_ids():
+    rng = RNG(32)
+    a = rng.uniform(size=(6, 4, 5)).astype(np.float32)
+    A = O.select_scores_f32(a)
+    tau = float(np.median(A))
+    m = O.select_active(a, 3, tau)
+    assert not np.any(m & (A <= np.float32(tau)))
+    assert np.all(m <= O.select_active(a, 3))
+    ids, off = O.select_ids(m)
+    assert np.all(np.diff(ids) > 0) and off[-1] == len(ids) == m.sum()
+    for z in range(6):
+        seg = ids[off[z]:off[z + 1]]
+        assert np.all(seg // 20 == z)
+
+
+def test_sparse_gradient_is_dense_gradient_masked():
+    # (d): the restricted update moves exactly the voxels in S, each by -lambda * dense grad
+    M, I, G = _tiny_problem(14)
+    _, g = O.loss_and_grad(M, G, I)
+    mask = O.select_active(M[..., 3], 2)
+    lam = 1e-3
+    new = O.apply_update(M, g, mask, lam, lam)
+    step = (M - new) / lam
+    np.testing.assert_allclose(step[mask], g[mask], rtol=1e-9, atol=1e-12)
+    assert np.all(step[~mask] == 0.0)
+    # k = D: S is every voxel, sparse = dense
+    full = O.select_active(M[..., 3], M.shape[0])
+    assert full.all()
+
+
+def test_descent_lemma_and_clamp():
+    M, I, G = _tiny_problem(15)
+    L0, g = O.loss_and_grad(M, G, I)
+    mask = O.select_active(M[..., 3], 2)
+    L1 = O.photometric_loss(O.render(O.apply_update(M, g, mask, 1e-3, 1e-3), G), I)
+    assert L1 < L0
+    big = O.apply_update(M, g, mask, 1e6, 1e6)
+    assert big.min() >= 0.0 and big.max() <= 1.0
+
+
+def test_bf16_round_matches_torch():
+    torch = pytest.importorskip("torch")
+    rng = RNG(33)
+    x = np.concatenate([rng.uniform(0, 1, 1000), rng.normal(size=1000),
+                        # exact halfway points between bf16 neighbours (ties to even)
+                        (np.arange(1, 200) * 2 + 1) * 2.0 ** -16 + 1.0]).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(O.bf16_round(x), ref)
+
+
+# ------------------------------------------------------------------ hierarchy
+def test_upsample_preserves_constants_and_ramps():
+    D, h, w = 2, 6, 7
+    M = np.full((D, h, w, 4), 0.37)
+    np.testing.assert_allclose(O.upsample2x(M), 0.37, atol=1e-15)
+    ys, xs = np.mgrid[0:h, 0:w].astype(float)
+    R = np.zeros((1, h, w, 4))
+    R[0, ..., 0] = 0.5 * xs + 0.25 * ys
+    U = O.upsample2x(R)[0, ..., 0]
+    Y, X = np.mgrid[0:2 * h, 0:2 * w].astype(float)
+    sx, sy = (X + 0.5) / 2 - 0.5, (Y + 0.5) / 2 - 0.5
+    inner = (X >= 1) & (X <= 2 * w - 2) & (Y >= 1) & (Y <= 2 * h - 2)
+    np.testing.assert_allclose(U[inner], (0.5 * sx + 0.25 * sy)[inner], atol=1e-12)
+    # edge clamp: the outermost fine pixels take the outermost coarse values
+    np.testing.assert_allclose(U[0, 0], R[0, 0, 0, 0])
+
+
+def test_downsample_box_mean():
+    rng = RNG(34)
+    img = rng.uniform(size=(2, 8, 6, 3))
+    d = O.downsample2x(img)
+    assert d.shape == (2, 4, 3, 3)
+    np.testing.assert_allclose(d[1, 2, 1], img[1, 4:6, 2:4].mean(axis=(0, 1)))
+    np.testing.assert_allclose(d.sum() * 4, img.sum())
+
+
+# ------------------------------------------------------------------ whole refine
+def test_refine_decreases_loss_on_tiny_scene():
+    sc = scenes.make_scene("c1")
+    gt = sc.gt_mpi()
+    K = sc.K_views()
+    G = O.view_to_ref_maps(sc.K_ref(), K, sc.R_views(), sc.t_views(), sc.depths)
+    targets = O.render(gt, G)
+    M, log = O.refine(sc.initial_mpi(), targets, sc.K_ref(), K, sc.R_views(), sc.t_views(),
+                      sc.depths, sc.iters, sc.k, lr_rgb=1.0, lr_alpha=1.0)
+    assert M.shape == gt.shape
+    assert log[1]["loss"] < log[0]["loss"]
+    assert all(e["active"] == sc.k * (M.shape[1] * M.shape[2]) // (4 ** (1 - e["level"]))
+               for e in log)
+
+
+def test_refine_from_ground_truth_stays_put():
+    sc = scenes.make_scene("c1")
+    w0, h0 = sc.shapes()[0]
+    gt0 = sc.rasterise(w0, h0)
+    K = sc.K_views()
+    # targets rendered at the coarse level from gt0, one level only: the GT is stationary
+    Kr0 = O.level_intrinsics(sc.K_ref(), sc.W, sc.H, w0, h0)
+    K0 = np.stack([O.level_intrinsics(k, sc.W, sc.H, w0, h0) for k in K])
+    G0 = O.view_to_ref_maps(Kr0, K0, sc.R_views(), sc.t_views(), sc.depths)
+    t0 = O.render(gt0, G0)
+    M, log = O.refine(gt0, t0, Kr0, K0, sc.R_views(), sc.t_views(), sc.depths, (2,), sc.k, 1.0, 1.0)
+    assert log[0]["loss"] == 0.0
+    np.testing.assert_array_equal(M, gt0)
