@@ -1,0 +1,239 @@
+/*
+ * hsgd.h -- C ABI of the MI355X (gfx950) HSGD library, libhsgd.so.
+ *
+ * Hierarchical Sparse Gradient Descent (RealLiFe, arXiv 2307.03017, Sec. 3.3) refines a
+ * multi-plane image (MPI, Sec. 3.1) against N posed source views. One iteration:
+ *   select  -- per reference pixel, keep the k planes with the largest compositing weight
+ *              A_z = a_z prod_{j<z}(1 - a_j) of the un-warped MPI (Eq. gradient, Eq. overA;
+ *              "Gradient Sparsification");
+ *   render  -- warp every plane into each view with the plane homography (Eq. homo) and
+ *              composite with the over operator (Eq. render, Eq. over);
+ *   grad    -- photometric loss against the views and its exact gradient, pushed back
+ *              through compositing and the bilinear warp, kept only on the selected voxels;
+ *   update  -- analytic descent (Eq. 4 with no prior) restored onto the selected voxels
+ *              (the M_{n+1} = M_n + R(., S) update), clamped to [0, 1].
+ * Levels run coarse to fine (Sec. 3.2: H/2^l x W/2^l), the MPI upsampled 2x in between.
+ *
+ * Conventions for every call:
+ *  - Layouts. MPI: [D][H][W][4] straight (non-premultiplied) RGBA in [0, 1], plane z = 0 the
+ *    nearest (the paper's d = D - z), FP32 or BF16 storage. Images: [N][H][W][3] FP32.
+ *    Views and the MPI share one H x W grid per level; pixel centres sit at integer
+ *    coordinates.
+ *  - Ownership. Every pointer passed in is CALLER-OWNED; the library never allocates,
+ *    frees or retains device memory. Pointers documented as "device" must be device
+ *    memory of the current HIP device; "host" pointers are ordinary host memory.
+ *    Scratch memory comes in through (ws, ws_bytes); size it with hsgd_workspace_bytes().
+ *  - Streams. Device work is enqueued on the given stream (NULL = the legacy default
+ *    stream) and the call returns before it runs. Calls on one workspace must not overlap.
+ *  - Errors. Arguments are validated before anything is enqueued; a failing call enqueues
+ *    nothing and leaves every output untouched, returns a negative hsgd_status and sets a
+ *    thread-local message (hsgd_last_error). A failed kernel launch returns HSGD_E_HIP.
+ *    Faults during execution surface at the caller's next stream synchronisation.
+ *  - Limits: 1 <= D <= 64, H, W >= 2, 1 <= N <= 64, 1 <= k <= D.
+ */
+#ifndef HSGD_H
+#define HSGD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HSGD_OK = 0,
+    HSGD_E_ARG = -1,        /* null pointer, bad scalar (k, tau, lr, level count ...) */
+    HSGD_E_SHAPE = -2,      /* inconsistent or out-of-range sizes                      */
+    HSGD_E_DTYPE = -3,      /* unknown storage type                                    */
+    HSGD_E_CAPACITY = -4,   /* output array too small (ids capacity)                   */
+    HSGD_E_WORKSPACE = -5,  /* ws missing or smaller than hsgd_workspace_bytes()       */
+    HSGD_E_HIP = -6         /* a HIP runtime call or kernel launch failed              */
+} hsgd_status;
+
+typedef enum { HSGD_FP32 = 0, HSGD_BF16 = 1 } hsgd_dtype;
+
+/* Per (view, plane) map from a view pixel (x, y, 1) to the reference pixel on that plane:
+ * the inverse of the plane homography H_i^{-1}(d_z) of Eq. (homo). 64 bytes.
+ *  G        row-major 3x3, normalised so G[8] = 1 (FP32 copy of the FP64 map);
+ *  is_shift 1 when the map is a pure translation (identity rotation, no z translation,
+ *           equal intrinsics). Then the reference position is (x + ix + fx, y + iy + fy)
+ *           exactly: ix, iy integers, fx, fy in [0, 1) rounded once from FP64. */
+typedef struct {
+    float G[9];
+    int32_t is_shift;
+    int32_t ix, iy;
+    float fx, fy;
+    int32_t pad[2];
+} hsgd_warp;
+
+/* An MPI level. rgba: device, [D][H][W][4] of float (HSGD_FP32) or bfloat16 (HSGD_BF16). */
+typedef struct {
+    void* rgba;
+    int32_t D, H, W;
+    int32_t dtype;
+} hsgd_mpi;
+
+/* N source views at one level. images: device [N][H][W][3] FP32 targets (may be NULL
+ * where documented); warps: device [N][D] hsgd_warp (from hsgd_build_warps). */
+typedef struct {
+    const float* images;
+    const hsgd_warp* warps;
+    int32_t N, H, W;
+    int32_t pad;
+} hsgd_views;
+
+/* Sparsification rule. k: planes kept per pixel (1..D). tau < 0: pure top-k (the paper's
+ * rule); tau >= 0 additionally drops planes whose score A_z <= tau. */
+typedef struct {
+    int32_t k;
+    float tau;
+} hsgd_select_params;
+
+/* Operation codes for hsgd_workspace_bytes. */
+enum { HSGD_OP_SELECT = 0, HSGD_OP_RENDER = 1, HSGD_OP_GRAD_STEP = 2, HSGD_OP_REFINE = 3 };
+
+/* Human-readable name of a status code (static string). */
+const char* hsgd_status_string(int32_t status);
+
+/* Detail of the last failing call on this thread ("" if none). */
+const char* hsgd_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t hsgd_version(void);
+
+/*
+ * hsgd_build_warps -- host, FP64 (Sec. 3.2, Eq. homo).
+ * Computes, for view i and plane z at depth depth[z] (plane n^T X = d, n = (0,0,1), in the
+ * reference camera frame), H = K_i R_i (I + R_i^{-1} t_i n^T / d) K_ref^{-1} (the reference
+ * pose is the identity: world = reference camera frame; poses map world to camera,
+ * x_cam = R x_world + t) and stores its inverse in out[i*D + z].
+ *  K_ref host [9]; K, R host [N][9] row-major; t host [N][3]; depth host [D] (> 0);
+ *  out host [N*D]. No device memory is touched; copy out to the device yourself.
+ * Errors: HSGD_E_ARG for null pointers, non-positive depths or a singular map;
+ *         HSGD_E_SHAPE for N or D out of range.
+ */
+hsgd_status hsgd_build_warps(const double* K_ref, const double* K, const double* R,
+                             const double* t, const double* depth, int32_t N, int32_t D,
+                             hsgd_warp* out);
+
+/*
+ * hsgd_level_intrinsics -- host. Intrinsics of a W x H camera resampled to Wl x Hl in
+ * pixel-index coordinates (focal lengths scale by Wl/W, Hl/H; a principal point c maps to
+ * (c + 0.5) s - 0.5), the camera of hierarchy level l (Sec. 3.2). K, out: host [9].
+ */
+hsgd_status hsgd_level_intrinsics(const double* K, int32_t W, int32_t H, int32_t Wl,
+                                  int32_t Hl, double* out);
+
+/*
+ * hsgd_workspace_bytes -- bytes of workspace needed by one call of `op` on an MPI of
+ * D x H x W with N views and k planes kept per pixel. For HSGD_OP_REFINE give the finest
+ * level's H, W and the number of levels L (ignored otherwise). Returns 0 on bad sizes.
+ */
+size_t hsgd_workspace_bytes(int32_t op, int32_t D, int32_t H, int32_t W, int32_t N,
+                            int32_t k, int32_t L);
+
+/*
+ * hsgd_select_active -- the sparse index set S (Sec. 3.3 "Gradient Sparsification";
+ * Fig. sparse (b)).
+ * For every reference pixel p, computes the scores of the un-warped MPI front to back in
+ * IEEE float32, exactly A_z = a_z * T_z, T_{z+1} = T_z * (1 - a_z), T_0 = 1 (no fused
+ * multiply-add, denormals kept; BF16 alpha is decoded exactly), and keeps the k planes
+ * with the largest A_z; equal scores go to the nearer (smaller z) plane; NaN scores rank
+ * last. With p.tau >= 0, kept planes with A_z <= tau are dropped.
+ *  mask      device [H][W] uint64: bit z set <=> voxel (z, p) in S.
+ *  ids       device [cap] int32 or NULL: S as ascending linear ids z*H*W + y*W + x
+ *            (plane-major, the original depth order kept). cap >= k*H*W required.
+ *  plane_off device [D+1] int32 or NULL: ids of plane z are ids[plane_off[z] ..
+ *            plane_off[z+1]).
+ *  n_active  device [1] int32 or NULL: |S|.
+ * ids, plane_off and n_active are all NULL or all non-NULL.
+ */
+hsgd_status hsgd_select_active(const hsgd_mpi* m, hsgd_select_params p, uint64_t* mask,
+                               int32_t* ids, int32_t cap, int32_t* plane_off,
+                               int32_t* n_active, void* ws, size_t ws_bytes,
+                               hipStream_t stream);
+
+/*
+ * hsgd_render -- novel/source view rendering I~_t = O(w_t(M)) (Eq. render, Eq. over).
+ * For every view pixel, each plane is sampled at the warped position with bilinear
+ * interpolation (zero outside the plane; colour and alpha interpolated separately) and
+ * composited front to back over a black background.
+ *  out_rgb  device [N][H][W][3] FP32 or NULL.
+ *  out_loss device [1] FP32 or NULL: L = 1/(2N) sum_i sum_p sum_ch (C - I)^2 against
+ *           v->images (which must then be non-NULL).
+ */
+hsgd_status hsgd_render(const hsgd_mpi* m, const hsgd_views* v, float* out_rgb,
+                        float* out_loss, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * hsgd_grad_step -- one sparse gradient step (Sec. 3.3 "Sparse Gradient Update" with the
+ * analytic update of Eq. 4).
+ * Computes g = dL/dM, the exact gradient of the dense rendering of all views, where
+ * dL/dI~ is (I~ - I)/N for the photometric loss (dimg == NULL; v->images required) or the
+ * given upstream gradient dimg (device [N][H][W][3], a vector-Jacobian product), through
+ * the over operator (colour weight a~_z T_z, alpha weight T_z <g, c~_z - B_z> with B_z the
+ * composite behind plane z from a back-to-front scan) and the transpose of the bilinear
+ * warp. Only voxels of S are kept:
+ *  mask  device [H][W] uint64 from hsgd_select_active, or NULL for every voxel (dense).
+ *  kcap  most bits set in any mask word (the k given to hsgd_select_active; D when
+ *        mask == NULL). Planes of a pixel beyond its first kcap set bits are treated as
+ *        not selected.
+ * Then, if lr_rgb or lr_alpha is non-zero, M[S] <- clamp(M[S] - (lr_rgb x3, lr_alpha) g,
+ * 0, 1) in place (BF16 storage: round to nearest even on store); voxels outside S are
+ * never written.
+ *  grad_out device [D][H][W][4] FP32 or NULL: g on S, 0 elsewhere (every entry written).
+ *  out_loss device [1] FP32 or NULL: the loss before the update (needs v->images).
+ */
+hsgd_status hsgd_grad_step(hsgd_mpi* m, const hsgd_views* v, const uint64_t* mask,
+                           int32_t kcap, const float* dimg, float lr_rgb, float lr_alpha,
+                           float* grad_out, float* out_loss, void* ws, size_t ws_bytes,
+                           hipStream_t stream);
+
+/*
+ * hsgd_upsample2x -- MPI level transition (Sec. 3.3: refine the upsampled MPI).
+ * fine = 2x bilinear upsampling of coarse per plane and channel, source coordinate
+ * (x + 0.5)/2 - 0.5 clamped to the edge. fine must be 2H x 2W with the same D and dtype.
+ */
+hsgd_status hsgd_upsample2x(const hsgd_mpi* coarse, hsgd_mpi* fine, hipStream_t stream);
+
+/*
+ * hsgd_downsample2x -- one level of the image pyramid (Sec. 3.2: H/2^l x W/2^l):
+ * out[n][y][x] = mean of the 2x2 block of images at (2y, 2x). images device
+ * [N][H][W][3] FP32 (H, W even), out device [N][H/2][W/2][3].
+ */
+hsgd_status hsgd_downsample2x(const float* images, int32_t N, int32_t H, int32_t W,
+                              float* out, hipStream_t stream);
+
+/*
+ * hsgd_refine -- the whole coarse-to-fine HSGD refinement (Sec. 3.3; Fig. pipeline).
+ *  levels  [L] MPI descriptors, coarsest first; levels[0].rgba holds the initial MPI and
+ *          is refined in place; levels[l] for l > 0 (2x the size of level l-1, same D and
+ *          dtype) is overwritten with the upsampled MPI and refined in place. The result
+ *          is levels[L-1].
+ *  views   [L] per-level views: warps built with that level's intrinsics; images of the
+ *          finest level required; images of a coarser level may be NULL, in which case
+ *          they are computed as 2x2 box means of the next finer level into the workspace.
+ *  iters   host [L] iterations per level (>= 0).
+ *  sel     sparsification rule (k, tau) used at every iteration.
+ *  loss_log device [sum(iters)] FP32 or NULL: loss of each iteration before its update.
+ */
+hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
+                        const int32_t* iters, hsgd_select_params sel, float lr_rgb,
+                        float lr_alpha, float* loss_log, void* ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+/*
+ * hsgd_convert -- storage conversion of n floats: FP32 -> BF16 (round to nearest even),
+ * BF16 -> FP32 (exact) or a plain copy for equal types. src, dst device.
+ */
+hsgd_status hsgd_convert(const void* src, int32_t src_dtype, void* dst, int32_t dst_dtype,
+                         size_t n, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSGD_H */

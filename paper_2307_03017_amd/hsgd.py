@@ -1,0 +1,351 @@
+"""Python binding of libhsgd (ctypes). Argument marshalling only: every step of the HSGD
+path runs in the library's HIP kernels; PyTorch supplies device memory and streams.
+
+The raw C entry points keep their C names (``hsgd_select_active``, ``hsgd_render``,
+``hsgd_grad_step``, ``hsgd_refine``, ...) and take torch tensors in place of pointers.
+The library must have been built (``python -m paper_2307_03017_amd.build``); importing
+this module without it raises, there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhsgd.so")
+
+HSGD_FP32, HSGD_BF16 = 0, 1
+OP_SELECT, OP_RENDER, OP_GRAD_STEP, OP_REFINE = 0, 1, 2, 3
+
+
+class HsgdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+class Warp(ctypes.Structure):
+    _fields_ = [("G", ctypes.c_float * 9), ("is_shift", ctypes.c_int32), ("ix", ctypes.c_int32),
+                ("iy", ctypes.c_int32), ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("pad", ctypes.c_int32 * 2)]
+
+
+class Mpi(ctypes.Structure):
+    _fields_ = [("rgba", ctypes.c_void_p), ("D", ctypes.c_int32), ("H", ctypes.c_int32),
+                ("W", ctypes.c_int32), ("dtype", ctypes.c_int32)]
+
+
+class Views(ctypes.Structure):
+    _fields_ = [("images", ctypes.c_void_p), ("warps", ctypes.c_void_p), ("N", ctypes.c_int32),
+                ("H", ctypes.c_int32), ("W", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class SelectParams(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("tau", ctypes.c_float)]
+
+
+assert ctypes.sizeof(Warp) == 64
+
+# name -> (restype, argtypes); mirrors include/hsgd.h
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+_F = ctypes.c_float
+_SIGS = {
+    "hsgd_status_string": (ctypes.c_char_p, [_I]),
+    "hsgd_last_error": (ctypes.c_char_p, []),
+    "hsgd_version": (_I, []),
+    "hsgd_build_warps": (_I, [_P, _P, _P, _P, _P, _I, _I, _P]),
+    "hsgd_level_intrinsics": (_I, [_P, _I, _I, _I, _I, _P]),
+    "hsgd_workspace_bytes": (ctypes.c_size_t, [_I, _I, _I, _I, _I, _I, _I]),
+    "hsgd_select_active": (_I, [ctypes.POINTER(Mpi), SelectParams, _P, _P, _I, _P, _P, _P,
+                                ctypes.c_size_t, _P]),
+    "hsgd_render": (_I, [ctypes.POINTER(Mpi), ctypes.POINTER(Views), _P, _P, _P, ctypes.c_size_t, _P]),
+    "hsgd_grad_step": (_I, [ctypes.POINTER(Mpi), ctypes.POINTER(Views), _P, _I, _P, _F, _F, _P, _P,
+                            _P, ctypes.c_size_t, _P]),
+    "hsgd_upsample2x": (_I, [ctypes.POINTER(Mpi), ctypes.POINTER(Mpi), _P]),
+    "hsgd_downsample2x": (_I, [_P, _I, _I, _I, _P, _P]),
+    "hsgd_refine": (_I, [ctypes.POINTER(Mpi), ctypes.POINTER(Views), _I, _P, SelectParams, _F, _F,
+                         _P, _P, ctypes.c_size_t, _P]),
+    "hsgd_convert": (_I, [_P, _I, _P, _I, ctypes.c_size_t, _P]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libhsgd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2307_03017_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols() -> list:
+    return list(_SIGS)
+
+
+def _check(status: int):
+    if status != 0:
+        L = lib()
+        raise HsgdError(status, f"{L.hsgd_status_string(status).decode()}: "
+                                f"{L.hsgd_last_error().decode()}")
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        if not t.is_contiguous():
+            raise ValueError("tensors passed to libhsgd must be contiguous")
+        return t.data_ptr()
+    raise TypeError(type(t))
+
+
+def _dev(t: torch.Tensor | None, what: str):
+    if t is not None and not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _f32(t: torch.Tensor | None, what: str):
+    if t is not None and t.dtype != torch.float32:
+        raise TypeError(f"{what} must be float32")
+
+
+# ---------------------------------------------------------------------------------------
+# descriptors
+# ---------------------------------------------------------------------------------------
+def mpi_desc(rgba: torch.Tensor) -> Mpi:
+    """Descriptor of an MPI tensor [D][H][W][4] (float32 or bfloat16, device)."""
+    if rgba.dim() != 4 or rgba.shape[-1] != 4:
+        raise ValueError("MPI must be [D][H][W][4]")
+    _dev(rgba, "MPI")
+    if rgba.dtype == torch.float32:
+        dt = HSGD_FP32
+    elif rgba.dtype == torch.bfloat16:
+        dt = HSGD_BF16
+    else:
+        raise TypeError("MPI must be float32 or bfloat16")
+    D, H, W, _ = rgba.shape
+    return Mpi(_ptr(rgba), D, H, W, dt)
+
+
+def views_desc(warps: torch.Tensor, N: int, H: int, W: int, images: torch.Tensor | None = None) -> Views:
+    _dev(warps, "warps")
+    _dev(images, "images")
+    _f32(images, "images")
+    if images is not None and tuple(images.shape) != (N, H, W, 3):
+        raise ValueError(f"images must be [{N}][{H}][{W}][3]")
+    return Views(_ptr(images), _ptr(warps), N, H, W, 0)
+
+
+def workspace(op: int, D: int, H: int, W: int, N: int, k: int, L: int = 1, device=None) -> torch.Tensor:
+    n = lib().hsgd_workspace_bytes(op, D, H, W, N, k, L)
+    if n == 0:
+        raise HsgdError(-1, f"invalid sizes for a workspace query (op={op}, D={D}, H={H}, W={W}, N={N}, k={k}, L={L})")
+    return torch.empty(n, dtype=torch.uint8, device=device or "cuda")
+
+
+# ---------------------------------------------------------------------------------------
+# host calls
+# ---------------------------------------------------------------------------------------
+def hsgd_build_warps(K_ref, K, R, t, depths) -> np.ndarray:
+    """FP64 plane maps for N views x D planes; returns a uint8 array [N][D][64] (hsgd_warp)."""
+    K_ref = np.ascontiguousarray(K_ref, dtype=np.float64).reshape(9)
+    K = np.ascontiguousarray(K, dtype=np.float64).reshape(-1, 9)
+    R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1, 9)
+    t = np.ascontiguousarray(t, dtype=np.float64).reshape(-1, 3)
+    depths = np.ascontiguousarray(depths, dtype=np.float64).reshape(-1)
+    N, D = K.shape[0], depths.shape[0]
+    if R.shape[0] != N or t.shape[0] != N:
+        raise ValueError("K, R, t must have one entry per view")
+    out = (Warp * (N * D))()
+    _check(lib().hsgd_build_warps(K_ref.ctypes.data, K.ctypes.data, R.ctypes.data, t.ctypes.data,
+                                  depths.ctypes.data, N, D, ctypes.addressof(out)))
+    return np.frombuffer(bytes(out), dtype=np.uint8).reshape(N, D, 64).copy()
+
+
+def warp_records(raw: np.ndarray) -> list:
+    """Decode hsgd_build_warps output into Warp structures (for inspection and tests)."""
+    buf = np.ascontiguousarray(raw, dtype=np.uint8).tobytes()
+    n = len(buf) // 64
+    arr = (Warp * n).from_buffer_copy(buf)
+    return list(arr)
+
+
+def hsgd_level_intrinsics(K, W: int, H: int, Wl: int, Hl: int) -> np.ndarray:
+    K = np.ascontiguousarray(K, dtype=np.float64).reshape(9)
+    out = np.empty(9, dtype=np.float64)
+    _check(lib().hsgd_level_intrinsics(K.ctypes.data, W, H, Wl, Hl, out.ctypes.data))
+    return out.reshape(3, 3)
+
+
+def level_warps(K_ref, K, R, t, depths, W: int, H: int, Wl: int, Hl: int, device="cuda") -> torch.Tensor:
+    """Warp table [N][D][64] bytes on the device for a Wl x Hl level of a W x H camera rig."""
+    Kr_l = hsgd_level_intrinsics(K_ref, W, H, Wl, Hl)
+    K_l = np.stack([hsgd_level_intrinsics(k, W, H, Wl, Hl) for k in np.asarray(K).reshape(-1, 3, 3)])
+    raw = hsgd_build_warps(Kr_l, K_l, R, t, depths)
+    return torch.from_numpy(raw).to(device)
+
+
+# ---------------------------------------------------------------------------------------
+# device calls
+# ---------------------------------------------------------------------------------------
+def hsgd_select_active(rgba: torch.Tensor, k: int, tau: float = -1.0, with_ids: bool = True,
+                       mask: torch.Tensor | None = None, stream=None):
+    """Returns mask (int64 [H][W], bit z = voxel (z, p) selected) and, if with_ids,
+    (ids int32 [k*H*W] capacity, plane_off int32 [D+1], n_active int32 [1])."""
+    m = mpi_desc(rgba)
+    dev = rgba.device
+    if mask is None:
+        mask = torch.empty((m.H, m.W), dtype=torch.int64, device=dev)
+    ids = plane_off = n_active = ws = None
+    cap = 0
+    if with_ids:
+        cap = k * m.H * m.W
+        ids = torch.empty(cap, dtype=torch.int32, device=dev)
+        plane_off = torch.empty(m.D + 1, dtype=torch.int32, device=dev)
+        n_active = torch.empty(1, dtype=torch.int32, device=dev)
+        ws = workspace(OP_SELECT, m.D, m.H, m.W, 1, k, device=dev)
+    _check(lib().hsgd_select_active(ctypes.byref(m), SelectParams(k, tau), _ptr(mask), _ptr(ids), cap,
+                                    _ptr(plane_off), _ptr(n_active), _ptr(ws),
+                                    0 if ws is None else ws.numel(), _stream(stream)))
+    if with_ids:
+        return mask, ids, plane_off, n_active
+    return mask
+
+
+def hsgd_render(rgba: torch.Tensor, warps: torch.Tensor, N: int, images: torch.Tensor | None = None,
+                want_rgb: bool = True, want_loss: bool = False, stream=None):
+    """Render N views ([N][H][W][3] float32) and/or the photometric loss against images."""
+    m = mpi_desc(rgba)
+    v = views_desc(warps, N, m.H, m.W, images)
+    dev = rgba.device
+    out = torch.empty((N, m.H, m.W, 3), dtype=torch.float32, device=dev) if want_rgb else None
+    loss = torch.empty(1, dtype=torch.float32, device=dev) if want_loss else None
+    ws = workspace(OP_RENDER, m.D, m.H, m.W, N, 1, device=dev) if want_loss else None
+    _check(lib().hsgd_render(ctypes.byref(m), ctypes.byref(v), _ptr(out), _ptr(loss), _ptr(ws),
+                             0 if ws is None else ws.numel(), _stream(stream)))
+    return out, loss
+
+
+def hsgd_grad_step(rgba: torch.Tensor, warps: torch.Tensor, N: int, images: torch.Tensor | None = None,
+                   mask: torch.Tensor | None = None, kcap: int | None = None,
+                   dimg: torch.Tensor | None = None, lr_rgb: float = 0.0, lr_alpha: float = 0.0,
+                   want_grad: bool = False, want_loss: bool = False, ws: torch.Tensor | None = None,
+                   stream=None):
+    """One sparse gradient step (in place on rgba when a learning rate is non-zero).
+    Returns (grad [D][H][W][4] float32 or None, loss [1] or None)."""
+    m = mpi_desc(rgba)
+    v = views_desc(warps, N, m.H, m.W, images)
+    _dev(mask, "mask")
+    _dev(dimg, "dimg")
+    _f32(dimg, "dimg")
+    if dimg is not None and tuple(dimg.shape) != (N, m.H, m.W, 3):
+        raise ValueError("dimg must be [N][H][W][3]")
+    if mask is not None and (mask.dtype != torch.int64 or tuple(mask.shape) != (m.H, m.W)):
+        raise ValueError("mask must be int64 [H][W]")
+    kc = m.D if mask is None else (kcap if kcap is not None else m.D)
+    dev = rgba.device
+    grad = torch.empty((m.D, m.H, m.W, 4), dtype=torch.float32, device=dev) if want_grad else None
+    loss = torch.empty(1, dtype=torch.float32, device=dev) if want_loss else None
+    if ws is None:
+        ws = workspace(OP_GRAD_STEP, m.D, m.H, m.W, N, kc, device=dev)
+    _check(lib().hsgd_grad_step(ctypes.byref(m), ctypes.byref(v), _ptr(mask), kc, _ptr(dimg),
+                                float(lr_rgb), float(lr_alpha), _ptr(grad), _ptr(loss), _ptr(ws),
+                                ws.numel(), _stream(stream)))
+    return grad, loss
+
+
+def hsgd_upsample2x(coarse: torch.Tensor, fine: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    c = mpi_desc(coarse)
+    if fine is None:
+        fine = torch.empty((c.D, 2 * c.H, 2 * c.W, 4), dtype=coarse.dtype, device=coarse.device)
+    f = mpi_desc(fine)
+    _check(lib().hsgd_upsample2x(ctypes.byref(c), ctypes.byref(f), _stream(stream)))
+    return fine
+
+
+def hsgd_downsample2x(images: torch.Tensor, stream=None) -> torch.Tensor:
+    _dev(images, "images")
+    _f32(images, "images")
+    N, H, W, _ = images.shape
+    out = torch.empty((N, H // 2, W // 2, 3), dtype=torch.float32, device=images.device)
+    _check(lib().hsgd_downsample2x(_ptr(images), N, H, W, _ptr(out), _stream(stream)))
+    return out
+
+
+def hsgd_convert(src: torch.Tensor, dtype: torch.dtype, stream=None) -> torch.Tensor:
+    """FP32 <-> BF16 storage conversion in the library's kernel (RNE to BF16)."""
+    code = {torch.float32: HSGD_FP32, torch.bfloat16: HSGD_BF16}
+    _dev(src, "src")
+    dst = torch.empty(src.shape, dtype=dtype, device=src.device)
+    _check(lib().hsgd_convert(_ptr(src), code[src.dtype], _ptr(dst), code[dtype], src.numel(),
+                              _stream(stream)))
+    return dst
+
+
+class RefinePlan:
+    """Everything hsgd_refine needs for one camera rig and hierarchy, prepared once:
+    per-level warp tables, MPI level buffers and the workspace (caller-owned memory)."""
+
+    def __init__(self, K_ref, K, R, t, depths, W: int, H: int, iters: Sequence[int], k: int,
+                 tau: float = -1.0, lr_rgb: float = 1.0, lr_alpha: float = 1.0,
+                 dtype: torch.dtype = torch.float32, device="cuda"):
+        L = len(iters)
+        self.L, self.iters, self.k, self.tau = L, tuple(int(i) for i in iters), int(k), float(tau)
+        self.lr_rgb, self.lr_alpha = float(lr_rgb), float(lr_alpha)
+        self.N = int(np.asarray(K).reshape(-1, 3, 3).shape[0])
+        self.D = int(len(depths))
+        self.W, self.H = W, H
+        self.shapes = [(W >> (L - 1 - l), H >> (L - 1 - l)) for l in range(L)]
+        self.warps = [level_warps(K_ref, K, R, t, depths, W, H, w, h, device) for (w, h) in self.shapes]
+        self.levels = [torch.empty((self.D, h, w, 4), dtype=dtype, device=device) for (w, h) in self.shapes]
+        self.ws = workspace(OP_REFINE, self.D, H, W, self.N, self.k, L, device=device)
+        self.loss_log = torch.zeros(max(1, sum(self.iters)), dtype=torch.float32, device=device)
+        self._iters = (ctypes.c_int32 * L)(*self.iters)
+
+    def descriptors(self, images: torch.Tensor, coarse_images: Sequence | None = None):
+        mpis = (Mpi * self.L)(*[mpi_desc(m) for m in self.levels])
+        vs = []
+        for l, (w, h) in enumerate(self.shapes):
+            img = images if l == self.L - 1 else (coarse_images[l] if coarse_images else None)
+            vs.append(views_desc(self.warps[l], self.N, h, w, img))
+        return mpis, (Views * self.L)(*vs)
+
+    def run(self, images: torch.Tensor, descriptors=None, stream=None):
+        """Refine levels[0] (the initial MPI, already written by the caller) up to levels[-1]."""
+        mpis, vs = descriptors or self.descriptors(images)
+        _check(lib().hsgd_refine(mpis, vs, self.L, self._iters, SelectParams(self.k, self.tau),
+                                 self.lr_rgb, self.lr_alpha, _ptr(self.loss_log), _ptr(self.ws),
+                                 self.ws.numel(), _stream(stream)))
+        return self.levels[-1]
+
+
+def hsgd_refine(init: torch.Tensor, images: torch.Tensor, K_ref, K, R, t, depths, iters, k,
+                tau: float = -1.0, lr_rgb: float = 1.0, lr_alpha: float = 1.0, stream=None):
+    """One-shot refinement: returns (final MPI, per-iteration losses)."""
+    N, H, W, _ = images.shape
+    plan = RefinePlan(K_ref, K, R, t, depths, W, H, iters, k, tau, lr_rgb, lr_alpha,
+                      dtype=init.dtype, device=init.device)
+    plan.levels[0].copy_(init)
+    plan.run(images, stream=stream)
+    return plan.levels[-1], plan.loss_log[:sum(plan.iters)]
