@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Benchmark: HSGD refinement of a 512x384 MPI with 32 planes, 4 views, 3 levels.
+
+One step = one whole hsgd_refine: target pyramid, then per level (128x96, 256x192,
+512x384) an MPI upsampling (levels > 0) and one iteration of select -> render + loss ->
+restricted adjoint -> sparse update, all in the library's HIP kernels. Inputs (seeded
+synthetic forward-facing scene, targets rendered by hsgd_render from the ground-truth MPI)
+are resident in HBM before the timed region; each step first restores the coarse initial
+MPI from a device copy (the refine updates it in place).
+
+Prints one JSON line. value = dense-equivalent voxel-updates per refine (sum over
+iterations of D*H_l*W_l = 8,257,536) x steps / wall time of the timed region.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "HSGD MPI voxel-updates/s at 512x384x32, 3 iters; p50/p99 frame latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1"])
+    ap.add_argument("--dtype", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="also run N launches of the library's plain FP32 copy kernel (256 MiB)")
+    return ap.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("hsgd_kernels.hip",):
+        with open(os.path.join(ROOT, "paper_2307_03017_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def grad_launch_bytes(D, shapes, iters, N, k, s):
+    """Algorithmic bytes of the gradient kernel's launches in one refine: per launch the MPI
+    read once (D*H*W*s), the targets (N*H*W*12), the plane mask (H*W*8) and the gradient of
+    the active voxels written once (k*H*W*16)."""
+    total = 0
+    launches = 0
+    for (w, h), n in zip(shapes, iters):
+        HW = w * h
+        total += n * (D * HW * s + N * HW * 12 + HW * 8 + k * HW * 16)
+        launches += n
+    return total, launches
+
+
+def refine_alg_bytes(D, shapes, iters, N, k, s):
+    """Algorithmic bytes of a whole refine (the method's minimum traffic): per level the
+    coarse MPI read and the upsampled MPI written (l > 0); per iteration one dense MPI read,
+    the FP32 targets and the read-modify-write of the active voxels with their int32 ids."""
+    total = 0
+    for l, ((w, h), n) in enumerate(zip(shapes, iters)):
+        HW = w * h
+        if l > 0:
+            pw, ph = shapes[l - 1]
+            total += D * pw * ph * s + D * HW * s
+        total += n * (D * HW * s + N * HW * 12 + k * HW * (4 + 2 * s))
+    return total
+
+
+def cpu_baseline(name):
+    """The FP64 oracle's refine of the same workload on the host, single-threaded."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import hsgd_oracle as O
+    from paper_2307_03017_amd import scenes
+
+    sc = scenes.make_scene(name)
+    G = O.view_to_ref_maps(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths)
+    with threadpool_limits(limits=1):
+        targets = O.render(sc.gt_mpi(), G)           # untimed input preparation
+        init = sc.initial_mpi()
+        t0 = time.perf_counter()
+        O.refine(init, targets, sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths,
+                 sc.iters, sc.k, 1.0, 1.0)
+        dt = time.perf_counter() - t0
+    dense = sum(n * sc.D * w * h for (w, h), n in zip(sc.shapes(), sc.iters))
+    return {"value": dense / dt, "unit": "voxel-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full 3-level refine of the same {sc.W}x{sc.H}x{sc.D} scene "
+                      f"(FP64 NumPy, {dt:.1f} s; targets rendered by the oracle, untimed)"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the HSGD path here has no multi-GPU "
+              "implementation. Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2307_03017_amd import hsgd, scenes
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    sc = scenes.make_scene(args.workload)
+    tdtype = torch.float32 if args.dtype == "fp32" else torch.bfloat16
+    s_bytes = 16 if args.dtype == "fp32" else 8
+    plan = hsgd.RefinePlan(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths,
+                           sc.W, sc.H, sc.iters, sc.k, lr_rgb=1.0, lr_alpha=1.0, dtype=tdtype,
+                           device=dev)
+    gt = torch.from_numpy(sc.gt_mpi().astype(np.float32)).to(dev)
+    targets, _ = hsgd.hsgd_render(gt, hsgd.level_warps(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(),
+                                                       sc.depths, sc.W, sc.H, sc.W, sc.H, dev), sc.N)
+    init32 = torch.from_numpy(sc.initial_mpi().astype(np.float32)).to(dev)
+    init = init32 if tdtype == torch.float32 else hsgd.hsgd_convert(init32, tdtype)
+    desc = plan.descriptors(targets)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        plan.levels[0].copy_(init)
+        plan.run(targets, desc)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    dense = sum(n * sc.D * w * h for (w, h), n in zip(plan.shapes, sc.iters))
+    active = sum(n * sc.k * w * h for (w, h), n in zip(plan.shapes, sc.iters))
+    K = args.steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    # timed region: the gradient kernel (dominant) is bracketed by events on its stream
+    with hsgd.KernelTimer([hsgd.K_GRAD]) as kt:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(K):
+            plan.levels[0].copy_(init)
+            ev[i][0].record(stream)
+            plan.run(targets, desc)
+            ev[i][1].record(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    wall = t1 - t0
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    final_loss = plan.loss_log.cpu().numpy().tolist()
+
+    n_grad, ms_grad = kt.result[hsgd.K_GRAD]
+    gbytes, glaunch = grad_launch_bytes(sc.D, plan.shapes, sc.iters, sc.N, sc.k, s_bytes)
+    achieved = gbytes * K / (ms_grad * 1e-3) / 1e9 if ms_grad > 0 else None
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", f"k_grad_traffic_{args.workload}_{args.dtype}.json")
+    if os.path.exists(tf):
+        with open(tf) as fh:
+            rec = json.load(fh)
+        if rec.get("kernel_source_hash") == kernel_source_hash():
+            traffic = rec.get("hbm_bytes_per_refine")
+
+    out = {
+        "metric": METRIC,
+        "value": dense * K / wall,
+        "unit": "voxel-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.dtype == "fp32" else "bf16-storage/f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"hsgd_refine {sc.W}x{sc.H}x{sc.D} planes, {sc.N} views, "
+                         f"{len(sc.iters)} levels {'->'.join(f'{w}x{h}' for w, h in plan.shapes)}, "
+                         f"iters {list(sc.iters)}, k={sc.k}, {args.dtype} storage"),
+            "dense_voxel_updates_per_refine": dense,
+            "active_voxel_updates_per_refine": active,
+        },
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "value_p50": dense / (float(np.percentile(lat, 50)) * 1e-3),
+        "active_voxel_updates_per_s": active * K / wall,
+        "loss_log": final_loss,
+        "roofline": {
+            "kernel": "k_grad",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": traffic,
+            "launches": n_grad,
+            "avg_launch_us": ms_grad * 1e3 / max(n_grad, 1),
+            "alg_bytes_per_launch": gbytes / glaunch,
+        },
+        "path_roofline": {
+            "alg_bytes_per_refine": refine_alg_bytes(sc.D, plan.shapes, sc.iters, sc.N, sc.k, s_bytes),
+        },
+    }
+    out["path_roofline"]["frac_at_p50"] = (out["path_roofline"]["alg_bytes_per_refine"]
+                                           / (out["p50_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS)
+
+    if args.calibrate_copy:
+        n = 64 * 1024 * 1024   # floats = 256 MiB
+        a = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
+        for _ in range(args.calibrate_copy):
+            hsgd.hsgd_convert(a, torch.float32)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = 2 * 4 * n
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

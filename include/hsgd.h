@@ -77,12 +77,16 @@ typedef struct {
 } hsgd_mpi;
 
 /* N source views at one level. images: device [N][H][W][3] FP32 targets (may be NULL
- * where documented); warps: device [N][D] hsgd_warp (from hsgd_build_warps). */
+ * where documented); warps: device [N][D] hsgd_warp (from hsgd_build_warps).
+ * flags: HSGD_VIEWS_SHIFT_ONLY when every warp record has is_shift = 1 (check the host
+ * copy with hsgd_warps_shift_only); the gradient then takes the deterministic
+ * translation path. Setting it for records that are not shifts gives wrong results. */
+#define HSGD_VIEWS_SHIFT_ONLY 1
 typedef struct {
     const float* images;
     const hsgd_warp* warps;
     int32_t N, H, W;
-    int32_t pad;
+    int32_t flags;
 } hsgd_views;
 
 /* Sparsification rule. k: planes kept per pixel (1..D). tau < 0: pure top-k (the paper's
@@ -118,6 +122,10 @@ int32_t hsgd_version(void);
 hsgd_status hsgd_build_warps(const double* K_ref, const double* K, const double* R,
                              const double* t, const double* depth, int32_t N, int32_t D,
                              hsgd_warp* out);
+
+/* hsgd_warps_shift_only -- host. 1 if all n records (host memory) are pure translations,
+ * else 0 (also for NULL or n < 1): the value for hsgd_views.flags. */
+int32_t hsgd_warps_shift_only(const hsgd_warp* warps, int32_t n);
 
 /*
  * hsgd_level_intrinsics -- host. Intrinsics of a W x H camera resampled to Wl x Hl in
@@ -231,6 +239,24 @@ hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
  */
 hsgd_status hsgd_convert(const void* src, int32_t src_dtype, void* dst, int32_t dst_dtype,
                          size_t n, hipStream_t stream);
+
+/*
+ * Kernel timing (tracing). Between hsgd_profile_begin and hsgd_profile_end, every launch
+ * of a kernel kind whose bit is set in kind_mask is bracketed by two HIP events recorded
+ * on the stream it is launched on. hsgd_profile_end waits for those events and adds up
+ * the durations; hsgd_profile_read returns launches and total milliseconds of one kind.
+ * One window at a time per process; not for use under stream capture.
+ */
+enum {
+    HSGD_K_SELECT = 0, HSGD_K_SCAN = 1, HSGD_K_COMPACT = 2, HSGD_K_RENDER = 3,
+    HSGD_K_GRAD = 4, HSGD_K_UPDATE = 5, HSGD_K_FILL = 6, HSGD_K_REDUCE = 7,
+    HSGD_K_UPSAMPLE = 8, HSGD_K_DOWNSAMPLE = 9, HSGD_K_CONVERT = 10, HSGD_K_COUNT = 11
+};
+hsgd_status hsgd_profile_begin(uint32_t kind_mask);
+hsgd_status hsgd_profile_end(void);
+hsgd_status hsgd_profile_read(int32_t kind, int64_t* launches, double* total_ms);
+/* Name of a kernel kind as it appears in profiler traces (static string, "" if unknown). */
+const char* hsgd_kernel_name(int32_t kind);
 
 #ifdef __cplusplus
 }

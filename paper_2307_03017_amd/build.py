@@ -36,6 +36,7 @@ SOURCES = [
     ("hsgd_kernels.hip", "device"),
     ("hsgd_api.cpp", "host"),
     ("hsgd_host.cpp", "host"),
+    ("hsgd_profile.cpp", "host"),
 ]
 
 

@@ -85,10 +85,13 @@ RenderWs render_ws(int H, int W, int N) {
 GradWs grad_ws(int D, int H, int W, int N, int kcap) {
     (void)D;
     GradWs w{};
-    w.nslots = (int64_t)H * W * kcap;
+    // one gradient slice per view (shift warps) or a single slice (general warps)
+    w.nslots = (int64_t)N * H * W * kcap;
     w.slots_off = 0;
     w.partial_off = align_up(sizeof(float) * 4 * (size_t)w.nslots);
-    w.nparts = ceil_div(W, kTileW) * ceil_div(H, kTileH) * N;
+    const int64_t general = ceil_div(W, kTileW) * ceil_div(H, kTileH) * N;
+    const int64_t shift = ceil_div(W + 1, kShiftOX) * ceil_div(H + 1, kShiftOY) * N;
+    w.nparts = general > shift ? general : shift;
     w.bytes = w.partial_off + align_up(sizeof(float) * w.nparts);
     return w;
 }
@@ -248,6 +251,13 @@ hsgd_status hsgd_build_warps(const double* K_ref, const double* K, const double*
     memcpy(out, tmp, sizeof(hsgd_warp) * (size_t)N * D);
     delete[] tmp;
     return HSGD_OK;
+}
+
+int32_t hsgd_warps_shift_only(const hsgd_warp* warps, int32_t n) {
+    if (!warps || n < 1) return 0;
+    for (int32_t i = 0; i < n; ++i)
+        if (warps[i].is_shift != 1) return 0;
+    return 1;
 }
 
 size_t hsgd_workspace_bytes(int32_t op, int32_t D, int32_t H, int32_t W, int32_t N,

@@ -17,6 +17,9 @@ constexpr size_t kAlign = 256;
 constexpr int kTileW = 64;
 constexpr int kTileH = 4;
 constexpr int kBlock = kTileW * kTileH;
+// Shift-warp gradient blocks: 64 x 8 rays of which 63 x 7 own a reference cell per plane.
+constexpr int kShiftOX = 63;
+constexpr int kShiftOY = 7;
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -63,6 +66,24 @@ struct RefineWs {
 RefineWs refine_ws(int D, int H, int W, int N, int k, int L);
 
 size_t dtype_bytes(int dtype);  // bytes per RGBA voxel, 0 for unknown
+
+// ---- kernel timing (hsgd_profile.cpp) ----
+constexpr int kNumKinds = HSGD_K_COUNT;
+const char* kind_name(int kind);
+// Brackets the launches made during its lifetime with events when profiling is on.
+class ProfScope {
+  public:
+    ProfScope(int kind, hipStream_t s);
+    ~ProfScope();
+    ProfScope(const ProfScope&) = delete;
+    ProfScope& operator=(const ProfScope&) = delete;
+
+  private:
+    int kind_;
+    hipStream_t s_;
+    void* a_ = nullptr;
+    void* b_ = nullptr;
+};
 
 // ---- kernel launchers (hsgd_kernels.hip); return hipSuccess or the launch error ----
 int launch_select(const hsgd_mpi& m, int k, float tau, uint64_t* mask, int32_t* ids, int cap,

@@ -372,14 +372,14 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
 // gradient: forward scan, residual, back-to-front adjoint scan, restricted scatter
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ void scatter_tap(float4* __restrict__ slots, const uint64_t* __restrict__ mask,
-                                            int kcap, uint64_t full, int z, int p, float w,
+                                            int kcap, int HW, uint64_t full, int z, int p, float w,
                                             const float4& g) {
     if (w == 0.0f) return;
     const uint64_t m = mask ? mask[p] : full;
     if (!((m >> z) & 1)) return;
     const int r = __popcll(m & ((1ull << z) - 1));
     if (r >= kcap) return;
-    float* dst = reinterpret_cast<float*>(slots + (size_t)p * kcap + r);
+    float* dst = reinterpret_cast<float*>(slots + (size_t)r * HW + p);
     atomicAdd(dst + 0, w * g.x);
     atomicAdd(dst + 1, w * g.y);
     atomicAdd(dst + 2, w * g.z);
@@ -454,10 +454,10 @@ __global__ __launch_bounds__(kBlock) void k_grad(const void* __restrict__ mpi, i
                 b0 = s.w * s.x + oa * b0;
                 b1 = s.w * s.y + oa * b1;
                 b2 = s.w * s.z + oa * b2;
-                scatter_tap(slots, mask, kcap, full, z, tp.i00, tp.w00, gs);
-                scatter_tap(slots, mask, kcap, full, z, tp.i10, tp.w10, gs);
-                scatter_tap(slots, mask, kcap, full, z, tp.i01, tp.w01, gs);
-                scatter_tap(slots, mask, kcap, full, z, tp.i11, tp.w11, gs);
+                scatter_tap(slots, mask, kcap, HW, full, z, tp.i00, tp.w00, gs);
+                scatter_tap(slots, mask, kcap, HW, full, z, tp.i10, tp.w10, gs);
+                scatter_tap(slots, mask, kcap, HW, full, z, tp.i01, tp.w01, gs);
+                scatter_tap(slots, mask, kcap, HW, full, z, tp.i11, tp.w11, gs);
             }
         }
     }
@@ -468,29 +468,246 @@ __global__ __launch_bounds__(kBlock) void k_grad(const void* __restrict__ mpi, i
     }
 }
 
+// ------------------------------------------------------------------------------------
+// gradient for pure-translation warps: owner-computes, no atomics, deterministic
+//
+// A workgroup takes a 64 x 8 block of view rays: 63 x 7 "owner" rays plus one halo column
+// on the left and one halo row on top. For plane z every owner (x, y) also owns the
+// reference cell (x + ix_z, y + iy_z): with a translation the four rays whose bilinear
+// footprint covers that cell are the owner and its left, upper and upper-left neighbours,
+// all in the block. The per-ray adjoints are combined horizontally across lanes with DPP
+// and vertically across waves through LDS, and each owner writes its cell's gradient once
+// into the view's slice of the slot buffer (rank-major [view][kcap][H*W]).
+// ------------------------------------------------------------------------------------
+constexpr int kSX = kShiftOX + 1, kSY = kShiftOY + 1;  // rays per block (with halo)
+constexpr int kOX = kShiftOX, kOY = kShiftOY;          // owner rays (= owned cells) per block and plane
+static_assert(kSX == 64, "one wave per row of rays");
+
+__device__ __forceinline__ float lane_from_next(float v) {   // lane i <- lane i+1 (63 <- 0)
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_from_prev(float v) {   // lane i <- lane i-1 (0 <- 0)
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float4 lane_from_next4(float4 v) {
+    return make_float4(lane_from_next(v.x), lane_from_next(v.y), lane_from_next(v.z), lane_from_next(v.w));
+}
+__device__ __forceinline__ float4 lane_from_prev4(float4 v) {
+    return make_float4(lane_from_prev(v.x), lane_from_prev(v.y), lane_from_prev(v.z), lane_from_prev(v.w));
+}
+
+// Block index -> tile index so that each XCD (blocks are dealt round-robin to the 8 XCDs)
+// works on a contiguous run of tiles: neighbouring tiles and the views of one tile share
+// MPI lines in that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
+struct ShiftRec {
+    int ix, iy;
+    float fx, fy;
+};
+
+// Sample plane z at the ray (x, y) of this lane for a shift warp. All 64 lanes must call it
+// together (the right-hand taps come from the next lane through DPP).
+template <int DT>
+__device__ __forceinline__ float4 shift_sample(const void* __restrict__ mpi, int zbase, int H, int W,
+                                               int x, int y, const ShiftRec& sh, int lane) {
+    const int X0 = x + sh.ix, Y0 = y + sh.iy;
+    const bool y0ok = (unsigned)Y0 < (unsigned)H, y1ok = (unsigned)(Y0 + 1) < (unsigned)H;
+    const bool x0ok = (unsigned)X0 < (unsigned)W, x1ok = (unsigned)(X0 + 1) < (unsigned)W;
+    const int cx0 = min(max(X0, 0), W - 1);
+    const int r0 = zbase + min(max(Y0, 0), H - 1) * W;
+    const int r1 = zbase + min(max(Y0 + 1, 0), H - 1) * W;
+    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 t00 = (y0ok && x0ok) ? Vox<DT>::load(mpi, r0 + cx0) : zero;
+    float4 t01 = (y1ok && x0ok) ? Vox<DT>::load(mpi, r1 + cx0) : zero;
+    float4 t10 = lane_from_next4(t00);
+    float4 t11 = lane_from_next4(t01);
+    if (lane == kSX - 1) {
+        const int cx1 = min(max(X0 + 1, 0), W - 1);
+        t10 = (y0ok && x1ok) ? Vox<DT>::load(mpi, r0 + cx1) : zero;
+        t11 = (y1ok && x1ok) ? Vox<DT>::load(mpi, r1 + cx1) : zero;
+    }
+    const float gx = 1.0f - sh.fx, gy = 1.0f - sh.fy;
+    float4 s;
+    s.x = (t00.x * gx + t10.x * sh.fx) * gy + (t01.x * gx + t11.x * sh.fx) * sh.fy;
+    s.y = (t00.y * gx + t10.y * sh.fx) * gy + (t01.y * gx + t11.y * sh.fx) * sh.fy;
+    s.z = (t00.z * gx + t10.z * sh.fx) * gy + (t01.z * gx + t11.z * sh.fx) * sh.fy;
+    s.w = (t00.w * gx + t10.w * sh.fx) * gy + (t01.w * gx + t11.w * sh.fx) * sh.fy;
+    return s;
+}
+
+// REGS: keep every plane's sample in registers between the two scans (D <= 32); otherwise
+// sample again in the back-to-front scan.
+template <int DT, int MAXD, bool REGS>
+__global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
+    const void* __restrict__ mpi, int D, int H, int W, int N, const hsgd_warp* __restrict__ warps,
+    const float* __restrict__ images, const float* __restrict__ dimg, const uint64_t* __restrict__ mask,
+    int kcap, float inv_n, float4* __restrict__ slots, float* __restrict__ partials, int ntx, int nty) {
+    __shared__ ShiftRec s_sh[MAXD];
+    __shared__ float4 s_h[2][kSX * kSY];
+    __shared__ float sred[kSX * kSY / 64];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int view = tile % N;
+    const int t2 = tile / N;
+    const int tx = t2 % ntx, ty = t2 / ntx;
+    for (int z = threadIdx.x; z < D; z += blockDim.x) {
+        const hsgd_warp& w = warps[(size_t)view * D + z];
+        s_sh[z] = ShiftRec{w.ix, w.iy, w.fx, w.fy};
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int x = tx * kOX - 1 + lane, y = ty * kOY - 1 + wv;
+    const bool valid = (unsigned)x < (unsigned)W && (unsigned)y < (unsigned)H;
+    const bool owner = lane >= 1 && wv >= 1;
+    const int HW = H * W;
+    const uint64_t full = D == 64 ? ~0ull : ((1ull << D) - 1);
+
+    float4 smp[REGS ? MAXD : 1];
+    float Ts[MAXD];
+    float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+#pragma unroll
+    for (int z = 0; z < MAXD; ++z) {
+        if (z < D) {
+            const float4 s = shift_sample<DT>(mpi, z * HW, H, W, x, y, s_sh[z], lane);
+            if (REGS) smp[z] = s;
+            Ts[z] = T;
+            const float wgt = T * s.w;
+            c0 += wgt * s.x;
+            c1 += wgt * s.y;
+            c2 += wgt * s.z;
+            T *= 1.0f - s.w;
+        }
+    }
+    float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, sq = 0.0f;
+    if (valid) {
+        const size_t pix = ((size_t)view * H + y) * W + x;
+        if (images) {
+            const float d0 = c0 - images[3 * pix + 0];
+            const float d1 = c1 - images[3 * pix + 1];
+            const float d2 = c2 - images[3 * pix + 2];
+            if (owner) sq = d0 * d0 + d1 * d1 + d2 * d2;
+            g0 = d0 * inv_n;
+            g1 = d1 * inv_n;
+            g2 = d2 * inv_n;
+        }
+        if (dimg) {
+            g0 = dimg[3 * pix + 0];
+            g1 = dimg[3 * pix + 1];
+            g2 = dimg[3 * pix + 2];
+        }
+    }
+    float b0 = 0.0f, b1 = 0.0f, b2 = 0.0f;   // composite behind plane z
+    float4* vslots = slots + (size_t)view * kcap * HW;
+#pragma unroll
+    for (int zz = 0; zz < MAXD; ++zz) {
+        const int z = MAXD - 1 - zz;
+        if (z < D) {
+            const ShiftRec sh = s_sh[z];
+            const float4 s = REGS ? smp[REGS ? z : 0] : shift_sample<DT>(mpi, z * HW, H, W, x, y, sh, lane);
+            const float Tz = Ts[z];
+            const float ca = s.w * Tz;
+            float4 a;
+            a.x = g0 * ca;
+            a.y = g1 * ca;
+            a.z = g2 * ca;
+            a.w = Tz * (g0 * (s.x - b0) + g1 * (s.y - b1) + g2 * (s.z - b2));
+            const float oa = 1.0f - s.w;
+            b0 = s.w * s.x + oa * b0;
+            b1 = s.w * s.y + oa * b1;
+            b2 = s.w * s.z + oa * b2;
+            // horizontal half of the transposed bilinear: this ray (weight 1 - fx) and the
+            // ray to its left (weight fx) both touch the owned cell's row
+            const float4 ap = lane_from_prev4(a);
+            const float gx = 1.0f - sh.fx;
+            float4 h;
+            h.x = a.x * gx + ap.x * sh.fx;
+            h.y = a.y * gx + ap.y * sh.fx;
+            h.z = a.z * gx + ap.z * sh.fx;
+            h.w = a.w * gx + ap.w * sh.fx;
+            float4* buf = s_h[z & 1];
+            buf[threadIdx.x] = h;
+            __syncthreads();
+            if (owner) {
+                const int X = x + sh.ix, Y = y + sh.iy;
+                if ((unsigned)X < (unsigned)W && (unsigned)Y < (unsigned)H) {
+                    const int p = Y * W + X;
+                    const uint64_t m = mask ? mask[p] : full;
+                    if ((m >> z) & 1) {
+                        const int r = __popcll(m & ((1ull << z) - 1));
+                        if (r < kcap) {
+                            const float4 hu = buf[threadIdx.x - 64];   // the row above
+                            const float gy = 1.0f - sh.fy;
+                            float4 c;
+                            c.x = h.x * gy + hu.x * sh.fy;
+                            c.y = h.y * gy + hu.y * sh.fy;
+                            c.z = h.z * gy + hu.z * sh.fy;
+                            c.w = h.w * gy + hu.w * sh.fy;
+                            vslots[(size_t)r * HW + p] = c;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (partials) {
+        const float tot = block_sum(sq, sred);
+        if (threadIdx.x == 0) partials[tile] = tot;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_fill_zero(float4* __restrict__ p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = i; j < n; j += stride) p[j] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-template <int DT>
-__global__ __launch_bounds__(256) void k_update(void* __restrict__ mpi, int D, int HW,
+// Sum the per-view gradient slices of every selected voxel, then apply the clamped descent
+// step in place and/or write the dense-masked gradient. With shift warps, a view's slice
+// holds a voxel only if the voxel lies in that view's owner coverage; outside it the view
+// contributes nothing (no ray of the view reaches the voxel) and the slot is not read.
+template <int DT, bool SHIFT>
+__global__ __launch_bounds__(256) void k_update(void* __restrict__ mpi, int D, int H, int W,
                                                 const uint64_t* __restrict__ mask, int kcap,
-                                                const float4* __restrict__ slots, float lr_rgb,
-                                                float lr_a, int do_update,
+                                                const float4* __restrict__ slots, int nslices,
+                                                const hsgd_warp* __restrict__ warps, int cover_w,
+                                                int cover_h, float lr_rgb, float lr_a, int do_update,
                                                 float4* __restrict__ grad_out) {
+    extern __shared__ int2 s_off[];   // [nslices][D] (ix, iy) when SHIFT
+    if (SHIFT) {
+        for (int i = threadIdx.x; i < nslices * D; i += blockDim.x) s_off[i] = make_int2(warps[i].ix, warps[i].iy);
+        __syncthreads();
+    }
+    const int HW = H * W;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= HW) return;
+    const int X = p % W, Y = p / W;
     const uint64_t full = D == 64 ? ~0ull : ((1ull << D) - 1);
     const uint64_t m = mask ? mask[p] : full;
-    const float4* sp = slots + (size_t)p * kcap;
+    auto grad_of = [&](int z, int r) {
+        float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int v = 0; v < nslices; ++v) {
+            if (SHIFT) {
+                const int2 o = s_off[v * D + z];
+                const int cx = X - o.x, cy = Y - o.y;
+                if ((unsigned)cx >= (unsigned)cover_w || (unsigned)cy >= (unsigned)cover_h) continue;
+            }
+            const float4 t = slots[((size_t)v * kcap + r) * HW + p];
+            g.x += t.x;
+            g.y += t.y;
+            g.z += t.z;
+            g.w += t.w;
+        }
+        return g;
+    };
     if (grad_out) {
         int r = 0;
         for (int z = 0; z < D; ++z) {
             float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
             if ((m >> z) & 1) {
-                if (r < kcap) g = sp[r];
+                if (r < kcap) g = grad_of(z, r);
                 ++r;
             }
             grad_out[(size_t)z * HW + p] = g;
@@ -502,7 +719,7 @@ __global__ __launch_bounds__(256) void k_update(void* __restrict__ mpi, int D, i
         while (b && r < kcap) {
             const int z = __ffsll((unsigned long long)b) - 1;
             b &= b - 1;
-            const float4 g = sp[r++];
+            const float4 g = grad_of(z, r++);
             float4 v = Vox<DT>::load(mpi, z * HW + p);
             v.x = fminf(fmaxf(v.x - lr_rgb * g.x, 0.0f), 1.0f);
             v.y = fminf(fmaxf(v.y - lr_rgb * g.y, 0.0f), 1.0f);
@@ -593,15 +810,22 @@ int launch_select(const hsgd_mpi& m, int k, float tau, uint64_t* mask, int32_t* 
     const SelectWs L = select_ws(m.D, m.H, m.W);
     int* counts = ids ? reinterpret_cast<int*>((char*)ws + L.counts_off) : nullptr;
     const dim3 grid((unsigned)ceil_div(HW, 256));
-    HSGD_DISPATCH_T(m.dtype, HSGD_DISPATCH_D(m.D, hipLaunchKernelGGL((k_select<DT, MD>), grid, dim3(256), 0, s,
-                                                                    m.rgba, m.D, HW, k, tau, mask, counts, L.nblk)));
+    {
+        ProfScope ps(HSGD_K_SELECT, s);
+        HSGD_DISPATCH_T(m.dtype, HSGD_DISPATCH_D(m.D, hipLaunchKernelGGL((k_select<DT, MD>), grid, dim3(256), 0, s,
+                                                                        m.rgba, m.D, HW, k, tau, mask, counts, L.nblk)));
+    }
     if (ids) {
         const int64_t n = (int64_t)m.D * L.nblk;
         const int nseg = (int)L.nseg;
         int* seg = reinterpret_cast<int*>((char*)ws + L.seg_off);
-        hipLaunchKernelGGL(k_scan_seg, dim3(nseg), dim3(256), 0, s, counts, n, seg);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, counts, L.nblk, m.D, seg, nseg,
-                           plane_off, n_active);
+        {
+            ProfScope ps(HSGD_K_SCAN, s);
+            hipLaunchKernelGGL(k_scan_seg, dim3(nseg), dim3(256), 0, s, counts, n, seg);
+            hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, counts, L.nblk, m.D, seg, nseg,
+                               plane_off, n_active);
+        }
+        ProfScope ps(HSGD_K_COMPACT, s);
         hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, s, mask, m.D, HW, counts, seg, L.nblk, ids, cap);
     }
     return (int)hipGetLastError();
@@ -612,10 +836,15 @@ int launch_render(const hsgd_mpi& m, const hsgd_views& v, float* out_rgb, float*
     const RenderWs L = render_ws(m.H, m.W, v.N);
     float* partials = out_loss ? reinterpret_cast<float*>((char*)ws + L.partial_off) : nullptr;
     const dim3 grid((unsigned)ceil_div(m.W, kTileW), (unsigned)ceil_div(m.H, kTileH), (unsigned)v.N);
-    HSGD_DISPATCH_T(m.dtype, hipLaunchKernelGGL((k_render<DT>), grid, dim3(kBlock), 0, s, m.rgba, m.D,
-                                                m.H, m.W, v.warps, v.images, out_rgb, partials));
-    if (out_loss)
+    {
+        ProfScope ps(HSGD_K_RENDER, s);
+        HSGD_DISPATCH_T(m.dtype, hipLaunchKernelGGL((k_render<DT>), grid, dim3(kBlock), 0, s, m.rgba, m.D,
+                                                    m.H, m.W, v.warps, v.images, out_rgb, partials));
+    }
+    if (out_loss) {
+        ProfScope ps(HSGD_K_REDUCE, s);
         hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, L.nparts, 0.5 / v.N, out_loss);
+    }
     return (int)hipGetLastError();
 }
 
@@ -626,37 +855,85 @@ int launch_grad_step(const hsgd_mpi& m, const hsgd_views& v, const uint64_t* mas
     const GradWs L = grad_ws(m.D, m.H, m.W, v.N, kcap);
     float4* slots = reinterpret_cast<float4*>((char*)ws + L.slots_off);
     float* partials = reinterpret_cast<float*>((char*)ws + L.partial_off);
-    const int fill_blocks = (int)std::min<int64_t>(ceil_div(L.nslots, 256), 4096);
-    hipLaunchKernelGGL(k_fill_zero, dim3(fill_blocks), dim3(256), 0, s, slots, L.nslots);
-    const dim3 grid((unsigned)ceil_div(m.W, kTileW), (unsigned)ceil_div(m.H, kTileH), (unsigned)v.N);
     const float inv_n = 1.0f / (float)v.N;
-    HSGD_DISPATCH_T(m.dtype, HSGD_DISPATCH_D(m.D, hipLaunchKernelGGL((k_grad<DT, MD>), grid, dim3(kBlock), 0, s,
-                                                                    m.rgba, m.D, m.H, m.W, v.warps, v.images, dimg,
-                                                                    mask, kcap, inv_n, slots,
-                                                                    out_loss ? partials : nullptr)));
+    const bool shift = (v.flags & HSGD_VIEWS_SHIFT_ONLY) != 0;
+    int64_t nparts;
+    int cover_w = 0, cover_h = 0;
+    if (shift) {
+        const int ntx = (int)ceil_div(m.W + 1, kOX), nty = (int)ceil_div(m.H + 1, kOY);
+        cover_w = ntx * kOX;
+        cover_h = nty * kOY;
+        nparts = (int64_t)ntx * nty * v.N;
+        const dim3 grid((unsigned)nparts);
+        ProfScope ps(HSGD_K_GRAD, s);
+        HSGD_DISPATCH_T(m.dtype, switch (maxd_class(m.D)) {
+            case 8: hipLaunchKernelGGL((k_grad_shift<DT, 8, true>), grid, dim3(kSX * kSY), 0, s, m.rgba, m.D, m.H, m.W,
+                                       v.N, v.warps, v.images, dimg, mask, kcap, inv_n, slots,
+                                       out_loss ? partials : nullptr, ntx, nty); break;
+            case 16: hipLaunchKernelGGL((k_grad_shift<DT, 16, true>), grid, dim3(kSX * kSY), 0, s, m.rgba, m.D, m.H, m.W,
+                                        v.N, v.warps, v.images, dimg, mask, kcap, inv_n, slots,
+                                        out_loss ? partials : nullptr, ntx, nty); break;
+            case 32: hipLaunchKernelGGL((k_grad_shift<DT, 32, true>), grid, dim3(kSX * kSY), 0, s, m.rgba, m.D, m.H, m.W,
+                                        v.N, v.warps, v.images, dimg, mask, kcap, inv_n, slots,
+                                        out_loss ? partials : nullptr, ntx, nty); break;
+            default: hipLaunchKernelGGL((k_grad_shift<DT, 64, false>), grid, dim3(kSX * kSY), 0, s, m.rgba, m.D, m.H, m.W,
+                                        v.N, v.warps, v.images, dimg, mask, kcap, inv_n, slots,
+                                        out_loss ? partials : nullptr, ntx, nty); break;
+        });
+    } else {
+        const int64_t nslots = (int64_t)kcap * HW;
+        const int fill_blocks = (int)std::min<int64_t>(ceil_div(nslots, 256), 4096);
+        {
+            ProfScope ps(HSGD_K_FILL, s);
+            hipLaunchKernelGGL(k_fill_zero, dim3(fill_blocks), dim3(256), 0, s, slots, nslots);
+        }
+        const dim3 grid((unsigned)ceil_div(m.W, kTileW), (unsigned)ceil_div(m.H, kTileH), (unsigned)v.N);
+        nparts = (int64_t)grid.x * grid.y * grid.z;
+        ProfScope ps(HSGD_K_GRAD, s);
+        HSGD_DISPATCH_T(m.dtype, HSGD_DISPATCH_D(m.D, hipLaunchKernelGGL((k_grad<DT, MD>), grid, dim3(kBlock), 0, s,
+                                                                        m.rgba, m.D, m.H, m.W, v.warps, v.images, dimg,
+                                                                        mask, kcap, inv_n, slots,
+                                                                        out_loss ? partials : nullptr)));
+    }
     const int do_update = (lr_rgb != 0.0f || lr_alpha != 0.0f) ? 1 : 0;
-    HSGD_DISPATCH_T(m.dtype, hipLaunchKernelGGL((k_update<DT>), dim3((unsigned)ceil_div(HW, 256)), dim3(256), 0, s,
-                                                m.rgba, m.D, HW, mask, kcap, slots, lr_rgb, lr_alpha, do_update,
-                                                reinterpret_cast<float4*>(grad_out)));
-    if (out_loss)
-        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, L.nparts, 0.5 / v.N, out_loss);
+    {
+        ProfScope ps(HSGD_K_UPDATE, s);
+        const dim3 grid((unsigned)ceil_div(HW, 256));
+        if (shift) {
+            const size_t lds = sizeof(int2) * (size_t)v.N * m.D;
+            HSGD_DISPATCH_T(m.dtype, hipLaunchKernelGGL((k_update<DT, true>), grid, dim3(256), lds, s, m.rgba, m.D, m.H,
+                                                        m.W, mask, kcap, slots, v.N, v.warps, cover_w, cover_h, lr_rgb,
+                                                        lr_alpha, do_update, reinterpret_cast<float4*>(grad_out)));
+        } else {
+            HSGD_DISPATCH_T(m.dtype, hipLaunchKernelGGL((k_update<DT, false>), grid, dim3(256), 0, s, m.rgba, m.D, m.H,
+                                                        m.W, mask, kcap, slots, 1, v.warps, 0, 0, lr_rgb, lr_alpha,
+                                                        do_update, reinterpret_cast<float4*>(grad_out)));
+        }
+    }
+    if (out_loss) {
+        ProfScope ps(HSGD_K_REDUCE, s);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, nparts, 0.5 / v.N, out_loss);
+    }
     return (int)hipGetLastError();
 }
 
 int launch_upsample(const hsgd_mpi& c, const hsgd_mpi& f, hipStream_t s) {
     const dim3 grid((unsigned)ceil_div((int64_t)f.H * f.W, 256), (unsigned)c.D);
+    ProfScope ps(HSGD_K_UPSAMPLE, s);
     HSGD_DISPATCH_T(c.dtype, hipLaunchKernelGGL((k_upsample<DT>), grid, dim3(256), 0, s, c.rgba, c.H, c.W, f.rgba));
     return (int)hipGetLastError();
 }
 
 int launch_downsample(const float* img, int N, int H, int W, float* out, hipStream_t s) {
     const dim3 grid((unsigned)ceil_div((int64_t)(H / 2) * (W / 2), 256), (unsigned)N);
+    ProfScope ps(HSGD_K_DOWNSAMPLE, s);
     hipLaunchKernelGGL(k_downsample, grid, dim3(256), 0, s, img, H, W, out);
     return (int)hipGetLastError();
 }
 
 int launch_convert(const void* src, int sdt, void* dst, int ddt, size_t n, hipStream_t s) {
     const dim3 grid((unsigned)ceil_div((int64_t)n, 256));
+    ProfScope ps(HSGD_K_CONVERT, s);
     if (sdt == HSGD_FP32 && ddt == HSGD_FP32)
         hipLaunchKernelGGL((k_convert<HSGD_FP32, HSGD_FP32>), grid, dim3(256), 0, s, src, dst, (int64_t)n);
     else if (sdt == HSGD_FP32)

@@ -42,7 +42,10 @@ class Mpi(ctypes.Structure):
 
 class Views(ctypes.Structure):
     _fields_ = [("images", ctypes.c_void_p), ("warps", ctypes.c_void_p), ("N", ctypes.c_int32),
-                ("H", ctypes.c_int32), ("W", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("H", ctypes.c_int32), ("W", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+HSGD_VIEWS_SHIFT_ONLY = 1
 
 
 class SelectParams(ctypes.Structure):
@@ -61,6 +64,7 @@ _SIGS = {
     "hsgd_version": (_I, []),
     "hsgd_build_warps": (_I, [_P, _P, _P, _P, _P, _I, _I, _P]),
     "hsgd_level_intrinsics": (_I, [_P, _I, _I, _I, _I, _P]),
+    "hsgd_warps_shift_only": (_I, [_P, _I]),
     "hsgd_workspace_bytes": (ctypes.c_size_t, [_I, _I, _I, _I, _I, _I, _I]),
     "hsgd_select_active": (_I, [ctypes.POINTER(Mpi), SelectParams, _P, _P, _I, _P, _P, _P,
                                 ctypes.c_size_t, _P]),
@@ -72,7 +76,15 @@ _SIGS = {
     "hsgd_refine": (_I, [ctypes.POINTER(Mpi), ctypes.POINTER(Views), _I, _P, SelectParams, _F, _F,
                          _P, _P, ctypes.c_size_t, _P]),
     "hsgd_convert": (_I, [_P, _I, _P, _I, ctypes.c_size_t, _P]),
+    "hsgd_profile_begin": (_I, [ctypes.c_uint32]),
+    "hsgd_profile_end": (_I, []),
+    "hsgd_profile_read": (_I, [_I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
+    "hsgd_kernel_name": (ctypes.c_char_p, [_I]),
 }
+
+K_SELECT, K_SCAN, K_COMPACT, K_RENDER, K_GRAD, K_UPDATE, K_FILL, K_REDUCE, K_UPSAMPLE, \
+    K_DOWNSAMPLE, K_CONVERT = range(11)
+K_COUNT = 11
 
 _lib = None
 
@@ -148,13 +160,36 @@ def mpi_desc(rgba: torch.Tensor) -> Mpi:
     return Mpi(_ptr(rgba), D, H, W, dt)
 
 
-def views_desc(warps: torch.Tensor, N: int, H: int, W: int, images: torch.Tensor | None = None) -> Views:
+class WarpTable:
+    """Device copy of an hsgd_build_warps table plus its HSGD_VIEWS_SHIFT_ONLY flag."""
+
+    def __init__(self, raw: np.ndarray, device="cuda"):
+        raw = np.ascontiguousarray(raw, dtype=np.uint8)
+        self.N, self.D = raw.shape[0], raw.shape[1]
+        self.raw = raw
+        self.flags = HSGD_VIEWS_SHIFT_ONLY if lib().hsgd_warps_shift_only(raw.ctypes.data, self.N * self.D) else 0
+        self.tensor = torch.from_numpy(raw).to(device)
+
+    @property
+    def shift_only(self) -> bool:
+        return bool(self.flags & HSGD_VIEWS_SHIFT_ONLY)
+
+
+def views_desc(warps, N: int, H: int, W: int, images: torch.Tensor | None = None) -> Views:
+    """warps: a WarpTable, or a raw device tensor of hsgd_warp records (then the general
+    warp path is used even for translations)."""
+    flags = 0
+    if isinstance(warps, WarpTable):
+        flags = warps.flags
+        warps = warps.tensor
     _dev(warps, "warps")
     _dev(images, "images")
     _f32(images, "images")
+    if warps.numel() < N * 64:
+        raise ValueError("warp table holds fewer than N records")
     if images is not None and tuple(images.shape) != (N, H, W, 3):
         raise ValueError(f"images must be [{N}][{H}][{W}][3]")
-    return Views(_ptr(images), _ptr(warps), N, H, W, 0)
+    return Views(_ptr(images), _ptr(warps), N, H, W, flags)
 
 
 def workspace(op: int, D: int, H: int, W: int, N: int, k: int, L: int = 1, device=None) -> torch.Tensor:
@@ -198,12 +233,12 @@ def hsgd_level_intrinsics(K, W: int, H: int, Wl: int, Hl: int) -> np.ndarray:
     return out.reshape(3, 3)
 
 
-def level_warps(K_ref, K, R, t, depths, W: int, H: int, Wl: int, Hl: int, device="cuda") -> torch.Tensor:
-    """Warp table [N][D][64] bytes on the device for a Wl x Hl level of a W x H camera rig."""
+def level_warps(K_ref, K, R, t, depths, W: int, H: int, Wl: int, Hl: int, device="cuda") -> WarpTable:
+    """Warp table (N x D records) on the device for a Wl x Hl level of a W x H camera rig."""
     Kr_l = hsgd_level_intrinsics(K_ref, W, H, Wl, Hl)
     K_l = np.stack([hsgd_level_intrinsics(k, W, H, Wl, Hl) for k in np.asarray(K).reshape(-1, 3, 3)])
     raw = hsgd_build_warps(Kr_l, K_l, R, t, depths)
-    return torch.from_numpy(raw).to(device)
+    return WarpTable(raw, device)
 
 
 # ---------------------------------------------------------------------------------------
@@ -301,6 +336,40 @@ def hsgd_convert(src: torch.Tensor, dtype: torch.dtype, stream=None) -> torch.Te
     _check(lib().hsgd_convert(_ptr(src), code[src.dtype], _ptr(dst), code[dtype], src.numel(),
                               _stream(stream)))
     return dst
+
+
+class KernelTimer:
+    """Context manager timing library kernels with HIP events on their launch streams.
+
+        with KernelTimer([K_GRAD]) as kt:
+            ...launches...
+        kt.result[K_GRAD] -> (launches, total_ms)
+    """
+
+    def __init__(self, kinds=None):
+        kinds = list(range(K_COUNT)) if kinds is None else list(kinds)
+        self.mask = 0
+        for k in kinds:
+            self.mask |= 1 << k
+        self.kinds = kinds
+        self.result = {}
+
+    def __enter__(self):
+        _check(lib().hsgd_profile_begin(self.mask))
+        return self
+
+    def __exit__(self, *exc):
+        _check(lib().hsgd_profile_end())
+        for k in self.kinds:
+            n = ctypes.c_int64()
+            ms = ctypes.c_double()
+            _check(lib().hsgd_profile_read(k, ctypes.byref(n), ctypes.byref(ms)))
+            self.result[k] = (n.value, ms.value)
+        return False
+
+
+def kernel_name(kind: int) -> str:
+    return lib().hsgd_kernel_name(kind).decode()
 
 
 class RefinePlan:

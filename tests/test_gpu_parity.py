@@ -329,3 +329,34 @@ def test_full_size_select_and_gradient_c2():
     assert np.all(g[~S] == 0.0)
     assert rel_err(g[S], g_ref[S]) <= GRAD_RTOL
     assert abs(loss.item() - L_ref) <= 1e-5 * L_ref
+
+
+# --------------------------------------------------------------------------------- paths
+@pytest.mark.parametrize("D", [8, 32, 64])
+def test_shift_path_deterministic_and_equal_to_general_path(D):
+    """The translation path (owner-computes, no atomics) is bitwise reproducible and agrees
+    with the general-warp path (atomics) on the same translation rig."""
+    N, W, H = 3, 150, 70
+    rg, M, I = problem(50 + D, N, D, W, H, 60.0, 0.1, lo=0.05, hi=0.95)
+    table = device_warps(hsgd, rg)
+    assert table.shift_only
+    Md, Id = to_dev(M), to_dev(I)
+    k = max(1, D // 8)
+    mask = hsgd.hsgd_select_active(Md, k, with_ids=False)
+    g1, l1 = hsgd.hsgd_grad_step(Md, table, N, images=Id, mask=mask, kcap=k, want_grad=True, want_loss=True)
+    g2, l2 = hsgd.hsgd_grad_step(Md, table, N, images=Id, mask=mask, kcap=k, want_grad=True, want_loss=True)
+    gg, lg = hsgd.hsgd_grad_step(Md, table.tensor, N, images=Id, mask=mask, kcap=k, want_grad=True,
+                                 want_loss=True)
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2) and torch.equal(l1, l2)
+    assert rel_err(g1.cpu().numpy(), gg.cpu().numpy()) <= 1e-5
+    assert abs(l1.item() - lg.item()) <= 1e-6 * lg.item()
+
+
+def test_shift_path_large_shifts_and_borders():
+    """Shifts of tens of pixels (beyond a tile) on a ragged frame, every plane active."""
+    N, D, W, H = 4, 12, 190, 83
+    rg, M, I = problem(60, N, D, W, H, 400.0, 0.1, lo=0.05, hi=0.95)   # up to 40 px
+    _, g_ref = O.loss_and_grad(M, oracle_maps(O, rg), I)
+    g, _ = hsgd.hsgd_grad_step(to_dev(M), device_warps(hsgd, rg), N, images=to_dev(I), want_grad=True)
+    assert rel_err(g.cpu().numpy(), g_ref) <= GRAD_RTOL
