@@ -32,11 +32,12 @@ hsgd_status hsgd_select_active(const hsgd_mpi* m, hsgd_select_params p, uint64_t
     if (ids && (int64_t)cap < (int64_t)p.k * m->H * m->W)
         return fail(HSGD_E_CAPACITY, "%s: cap=%d < k*H*W=%lld", fn, cap,
                     (long long)p.k * m->H * m->W);
-    if (ids) {
-        st = check_ws(ws, ws_bytes, select_ws(m->D, m->H, m->W).bytes);
-        if (st) return st;
-    }
-    return hip_status(launch_select(*m, p.k, p.tau, mask, ids, cap, plane_off, n_active, ws, stream), fn);
+    if (!ids) return hip_status(launch_select(*m, p.k, p.tau, mask, nullptr, nullptr, stream), fn);
+    const ActiveLayout L = active_ws(m->D, m->H, m->W, cap, false);
+    st = check_ws(ws, ws_bytes, L.bytes);
+    if (st) return st;
+    const ActiveSet as = active_at(ws, L, ids, n_active);
+    return hip_status(launch_select(*m, p.k, p.tau, mask, &as, plane_off, stream), fn);
 }
 
 hsgd_status hsgd_render(const hsgd_mpi* m, const hsgd_views* v, float* out_rgb,
@@ -69,10 +70,16 @@ hsgd_status hsgd_grad_step(hsgd_mpi* m, const hsgd_views* v, const uint64_t* mas
     if (kcap < 1 || kcap > m->D) return fail(HSGD_E_ARG, "%s: kcap=%d outside [1, D=%d]", fn, kcap, m->D);
     if (!std::isfinite(lr_rgb) || !std::isfinite(lr_alpha))
         return fail(HSGD_E_ARG, "%s: learning rates must be finite", fn);
-    st = check_ws(ws, ws_bytes, grad_ws(m->D, m->H, m->W, v->N, kcap).bytes);
+    const GradWs L = grad_ws(m->D, m->H, m->W, v->N, kcap);
+    st = check_ws(ws, ws_bytes, L.bytes);
     if (st) return st;
-    return hip_status(launch_grad_step(*m, *v, mask, kcap, dimg, lr_rgb, lr_alpha, grad_out,
-                                       out_loss, ws, stream), fn);
+    const ActiveSet as = active_at(ws, L.act);
+    int e = launch_active_from_mask(m->D, m->H, m->W, mask, kcap, as, stream);
+    if (e) return hip_status(e, fn);
+    float4* slots = reinterpret_cast<float4*>((char*)ws + L.slots_off);
+    float* partials = reinterpret_cast<float*>((char*)ws + L.partial_off);
+    return hip_status(launch_grad_step(*m, *v, as, dimg, lr_rgb, lr_alpha, grad_out, out_loss, slots,
+                                       partials, stream), fn);
 }
 
 hsgd_status hsgd_upsample2x(const hsgd_mpi* coarse, hsgd_mpi* fine, hipStream_t stream) {
@@ -158,8 +165,8 @@ hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
         if (e) return hip_status(e, fn);
         img[l] = dst;
     }
-    uint64_t* mask = reinterpret_cast<uint64_t*>((char*)ws + R.mask_off);
-    void* inner = (char*)ws + R.inner_off;
+    // one workspace region sized for the finest level serves every level
+    char* inner = (char*)ws + R.inner_off;
     int it_global = 0;
     for (int l = 0; l < L; ++l) {
         if (l > 0) {
@@ -168,11 +175,15 @@ hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
         }
         hsgd_views v = views[l];
         v.images = img[l];
+        const GradWs G = grad_ws(levels[l].D, levels[l].H, levels[l].W, N, sel.k);
+        const ActiveSet as = active_at(inner, G.act);
+        float4* slots = reinterpret_cast<float4*>(inner + G.slots_off);
+        float* partials = reinterpret_cast<float*>(inner + G.partial_off);
         for (int it = 0; it < iters[l]; ++it, ++it_global) {
-            int e = launch_select(levels[l], sel.k, sel.tau, mask, nullptr, 0, nullptr, nullptr, inner, stream);
+            int e = launch_select(levels[l], sel.k, sel.tau, nullptr, &as, nullptr, stream);
             if (e) return hip_status(e, fn);
-            e = launch_grad_step(levels[l], v, mask, sel.k, nullptr, lr_rgb, lr_alpha, nullptr,
-                                 loss_log ? loss_log + it_global : nullptr, inner, stream);
+            e = launch_grad_step(levels[l], v, as, nullptr, lr_rgb, lr_alpha, nullptr,
+                                 loss_log ? loss_log + it_global : nullptr, slots, partials, stream);
             if (e) return hip_status(e, fn);
         }
     }

@@ -64,14 +64,41 @@ hsgd_status check_ws(void* ws, size_t ws_bytes, size_t need) {
     return HSGD_OK;
 }
 
-SelectWs select_ws(int D, int H, int W) {
-    SelectWs w{};
-    w.nblk = ceil_div((int64_t)H * W, 64);
-    w.nseg = ceil_div((int64_t)D * w.nblk, kScanSeg);
-    w.counts_off = 0;
-    w.seg_off = align_up(sizeof(int32_t) * (size_t)D * w.nblk);
-    w.bytes = w.seg_off + align_up(sizeof(int32_t) * (size_t)w.nseg);
-    return w;
+ActiveLayout active_ws(int D, int H, int W, int64_t cap, bool with_ids) {
+    ActiveLayout L{};
+    L.nblk = ceil_div((int64_t)H * W, 64);
+    L.nseg = ceil_div((int64_t)D * L.nblk, kScanSeg);
+    L.cap = cap;
+    size_t o = 0;
+    L.bal_off = o;
+    o += align_up(sizeof(uint64_t) * (size_t)D * L.nblk);
+    L.off_off = o;
+    o += align_up(sizeof(int32_t) * (size_t)D * L.nblk);
+    L.seg_off = o;
+    o += align_up(sizeof(int32_t) * (size_t)L.nseg);
+    L.ids_off = L.nact_off = 0;
+    if (with_ids) {
+        L.ids_off = o;
+        o += align_up(sizeof(int32_t) * (size_t)cap);
+        L.nact_off = o;
+        o += align_up(sizeof(int32_t));
+    }
+    L.bytes = o;
+    return L;
+}
+
+ActiveSet active_at(void* ws, const ActiveLayout& L, int* ids, int* nact) {
+    char* b = static_cast<char*>(ws);
+    ActiveSet a;
+    a.bal = reinterpret_cast<uint64_t*>(b + L.bal_off);
+    a.off = reinterpret_cast<int*>(b + L.off_off);
+    a.seg = reinterpret_cast<int*>(b + L.seg_off);
+    a.ids = ids ? ids : reinterpret_cast<int*>(b + L.ids_off);
+    a.nact = nact ? nact : reinterpret_cast<int*>(b + L.nact_off);
+    a.nblk = L.nblk;
+    a.nseg = L.nseg;
+    a.cap = L.cap;
+    return a;
 }
 
 RenderWs render_ws(int H, int W, int N) {
@@ -83,12 +110,11 @@ RenderWs render_ws(int H, int W, int N) {
 }
 
 GradWs grad_ws(int D, int H, int W, int N, int kcap) {
-    (void)D;
     GradWs w{};
-    // one gradient slice per view (shift warps) or a single slice (general warps)
-    w.nslots = (int64_t)N * H * W * kcap;
-    w.slots_off = 0;
-    w.partial_off = align_up(sizeof(float) * 4 * (size_t)w.nslots);
+    const int64_t cap = (int64_t)kcap * H * W;
+    w.act = active_ws(D, H, W, cap, true);
+    w.slots_off = w.act.bytes;
+    w.partial_off = w.slots_off + align_up(sizeof(float) * 4 * (size_t)N * cap);
     const int64_t general = ceil_div(W, kTileW) * ceil_div(H, kTileH) * N;
     const int64_t shift = ceil_div(W + 1, kShiftOX) * ceil_div(H + 1, kShiftOY) * N;
     w.nparts = general > shift ? general : shift;
@@ -104,12 +130,8 @@ RefineWs refine_ws(int D, int H, int W, int N, int k, int L) {
         w.pyr_off[l] = off;
         off += align_up(sizeof(float) * 3 * (size_t)N * (H / s) * (W / s));
     }
-    w.mask_off = off;
-    off += align_up(sizeof(uint64_t) * (size_t)H * W);
     w.inner_off = off;
-    size_t inner = grad_ws(D, H, W, N, k).bytes;
-    size_t sel = select_ws(D, H, W).bytes;
-    off += inner > sel ? inner : sel;
+    off += grad_ws(D, H, W, N, k).bytes;
     w.bytes = off;
     return w;
 }
@@ -264,7 +286,7 @@ size_t hsgd_workspace_bytes(int32_t op, int32_t D, int32_t H, int32_t W, int32_t
                             int32_t k, int32_t L) {
     if (D < 1 || D > kMaxD || H < 2 || W < 2 || N < 1 || N > kMaxN) return 0;
     switch (op) {
-        case HSGD_OP_SELECT: return select_ws(D, H, W).bytes;
+        case HSGD_OP_SELECT: return active_ws(D, H, W, 0, false).bytes;
         case HSGD_OP_RENDER: return render_ws(H, W, N).bytes;
         case HSGD_OP_GRAD_STEP:
             if (k < 1 || k > D) return 0;

@@ -17,8 +17,8 @@ constexpr size_t kAlign = 256;
 constexpr int kTileW = 64;
 constexpr int kTileH = 4;
 constexpr int kBlock = kTileW * kTileH;
-// Shift-warp gradient blocks: 64 x 8 rays of which 63 x 7 own a reference cell per plane.
-constexpr int kShiftOX = 63;
+// Shift-warp gradient blocks: 64 x 8 lanes of which 62 x 7 own a reference cell per plane.
+constexpr int kShiftOX = 62;
 constexpr int kShiftOY = 7;
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -35,13 +35,27 @@ hsgd_status check_views(const hsgd_views* v, const hsgd_mpi* m, bool need_images
 hsgd_status check_ws(void* ws, size_t ws_bytes, size_t need);
 
 // ---- workspace layouts (hsgd_host.cpp) ----
-// select: per (plane, 64-pixel block) counts, plane-major.
-struct SelectWs {
-    size_t counts_off, seg_off, bytes;
-    int64_t nblk, nseg;
-};
 constexpr int kScanSeg = 4096;  // counts scanned per workgroup
-SelectWs select_ws(int D, int H, int W);
+
+// The active set S as the kernels use it: for every (plane, 64-pixel block) the ballot
+// word of selected pixels and the offset of the block in the plane-major compact order,
+// the segment totals of the offset scan, the compact linear ids and |S|.
+struct ActiveLayout {
+    size_t bal_off, off_off, seg_off, ids_off, nact_off, bytes;
+    int64_t nblk, nseg, cap;
+};
+// with_ids = false: the caller provides ids and |S| (hsgd_select_active).
+ActiveLayout active_ws(int D, int H, int W, int64_t cap, bool with_ids);
+
+struct ActiveSet {
+    uint64_t* bal;
+    int* off;
+    int* seg;
+    int* ids;
+    int* nact;
+    int64_t nblk, nseg, cap;
+};
+ActiveSet active_at(void* ws, const ActiveLayout& L, int* ids = nullptr, int* nact = nullptr);
 
 // render: one FP32 loss partial per workgroup.
 struct RenderWs {
@@ -50,18 +64,20 @@ struct RenderWs {
 };
 RenderWs render_ws(int H, int W, int N);
 
-// grad_step: FP32 gradient slots [H*W][kcap][4] + loss partials.
+// grad_step: the active set (capacity kcap*H*W), one FP32 gradient slice per view over S
+// ([N][cap] float4) and the loss partials.
 struct GradWs {
+    ActiveLayout act;
     size_t slots_off, partial_off, bytes;
-    int64_t nslots, nparts;
+    int64_t nparts;
 };
 GradWs grad_ws(int D, int H, int W, int N, int kcap);
 
-// refine: target pyramid below the finest level, the mask, and the largest select /
-// grad_step workspaces (shared region).
+// refine: the target pyramid below the finest level, then the finest level's grad_step
+// workspace (reused by every level).
 struct RefineWs {
     size_t pyr_off[16];
-    size_t mask_off, inner_off, bytes;
+    size_t inner_off, bytes;
 };
 RefineWs refine_ws(int D, int H, int W, int N, int k, int L);
 
@@ -86,13 +102,17 @@ class ProfScope {
 };
 
 // ---- kernel launchers (hsgd_kernels.hip); return hipSuccess or the launch error ----
-int launch_select(const hsgd_mpi& m, int k, float tau, uint64_t* mask, int32_t* ids, int cap,
-                  int32_t* plane_off, int32_t* n_active, void* ws, hipStream_t s);
+// select: mask (nullable) and, when as != NULL, the active set (plane_off nullable).
+int launch_select(const hsgd_mpi& m, int k, float tau, uint64_t* mask, const ActiveSet* as,
+                  int32_t* plane_off, hipStream_t s);
+// the active set of a caller's mask (NULL mask: every voxel), first kcap bits per pixel.
+int launch_active_from_mask(int D, int H, int W, const uint64_t* mask, int kcap,
+                            const ActiveSet& as, hipStream_t s);
 int launch_render(const hsgd_mpi& m, const hsgd_views& v, float* out_rgb, float* out_loss,
                   void* ws, hipStream_t s);
-int launch_grad_step(const hsgd_mpi& m, const hsgd_views& v, const uint64_t* mask,
-                     int kcap, const float* dimg, float lr_rgb, float lr_alpha,
-                     float* grad_out, float* out_loss, void* ws, hipStream_t s);
+int launch_grad_step(const hsgd_mpi& m, const hsgd_views& v, const ActiveSet& as, const float* dimg,
+                     float lr_rgb, float lr_alpha, float* grad_out, float* out_loss, float4* slots,
+                     float* partials, hipStream_t s);
 int launch_upsample(const hsgd_mpi& coarse, const hsgd_mpi& fine, hipStream_t s);
 int launch_downsample(const float* img, int N, int H, int W, float* out, hipStream_t s);
 int launch_convert(const void* src, int sdt, void* dst, int ddt, size_t n, hipStream_t s);

@@ -42,6 +42,13 @@ struct Vox<HSGD_FP32> {
     static __device__ __forceinline__ void store(void* base, int i, float4 v) {
         reinterpret_cast<float4*>(base)[i] = v;
     }
+    // voxel `col` of the row starting at `row` (row uniform across the wave)
+    static __device__ __forceinline__ float4 load_row(const char* row, unsigned col) {
+        return *reinterpret_cast<const float4*>(row + (col << 4));
+    }
+    static __device__ __forceinline__ const char* row_ptr(const void* base, int i) {
+        return reinterpret_cast<const char*>(base) + (size_t)(unsigned)i * 16;
+    }
 };
 
 template <>
@@ -59,6 +66,14 @@ struct Vox<HSGD_BF16> {
         r.x = f32_to_bf16_bits(v.x) | (f32_to_bf16_bits(v.y) << 16);
         r.y = f32_to_bf16_bits(v.z) | (f32_to_bf16_bits(v.w) << 16);
         reinterpret_cast<uint2*>(base)[i] = r;
+    }
+    static __device__ __forceinline__ float4 load_row(const char* row, unsigned col) {
+        const uint2 r = *reinterpret_cast<const uint2*>(row + (col << 3));
+        return make_float4(__uint_as_float(r.x << 16), __uint_as_float(r.x & 0xffff0000u),
+                           __uint_as_float(r.y << 16), __uint_as_float(r.y & 0xffff0000u));
+    }
+    static __device__ __forceinline__ const char* row_ptr(const void* base, int i) {
+        return reinterpret_cast<const char*>(base) + (size_t)(unsigned)i * 8;
     }
 };
 
@@ -150,77 +165,120 @@ __device__ __forceinline__ void load_warps(hsgd_warp* sw, const hsgd_warp* warps
 }
 
 // ------------------------------------------------------------------------------------
-// select
+// select: scores, top-k, and the active-set structures
 // ------------------------------------------------------------------------------------
+// Per pixel p: A_z = fl(a_z T_z), T_{z+1} = fl(T_z fl(1 - a_z)) front to back on the
+// un-warped MPI, then the k largest A_z (equal scores: the nearer plane), then the optional
+// threshold. Returns the plane bitmask of p. FP32 contraction is off for this function.
 template <int DT, int MAXD>
-__global__ __launch_bounds__(256) void k_select(const void* __restrict__ mpi, int D, int HW,
-                                                int k, float tau, uint64_t* __restrict__ mask,
-                                                int* __restrict__ counts, int64_t nblk) {
+__device__ __forceinline__ uint64_t select_bits(const void* __restrict__ mpi, int D, int HW, int p,
+                                                int k, float tau) {
 #pragma clang fp contract(off)
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    float A[MAXD];
+    float T = 1.0f;
+#pragma unroll
+    for (int z = 0; z < MAXD; ++z) {
+        if (z < D) {
+            const float a = Vox<DT>::alpha(mpi, z * HW + p);
+            const float s = a * T;
+            A[z] = (s == s) ? s : -INFINITY;   // NaN ranks last
+            T = T * (1.0f - a);
+        }
+    }
+    const uint64_t full = D == 64 ? ~0ull : ((1ull << D) - 1);
+    const int kk = min(k, D);
     uint64_t sel = 0;
-    if (p < HW) {
-        float A[MAXD];
-        float T = 1.0f;
-#pragma unroll
-        for (int z = 0; z < MAXD; ++z) {
-            if (z < D) {
-                const float a = Vox<DT>::alpha(mpi, z * HW + p);
-                const float s = a * T;                  // A_z = fl(a_z * T_z)
-                A[z] = (s == s) ? s : -INFINITY;        // NaN ranks last
-                T = T * (1.0f - a);                     // T_{z+1} = fl(T_z * fl(1 - a_z))
-            }
-        }
-        const int kk = min(k, D);
-        if (kk == D) {
-            sel = D == 64 ? ~0ull : ((1ull << D) - 1);
-        } else if (2 * kk <= D) {
-            // kk passes: best remaining score, the nearer plane on equal scores
-            for (int j = 0; j < kk; ++j) {
-                int best = -1;
-                float bestA = 0.0f;
-#pragma unroll
-                for (int z = 0; z < MAXD; ++z)
-                    if (z < D && !((sel >> z) & 1) && (best < 0 || A[z] > bestA)) {
-                        best = z;
-                        bestA = A[z];
-                    }
-                sel |= 1ull << best;
-            }
-        } else {
-            // D - kk passes removing the worst: lowest score, the farther plane on ties
-            uint64_t out = 0;
-            for (int j = 0; j < D - kk; ++j) {
-                int worst = -1;
-                float worstA = 0.0f;
-#pragma unroll
-                for (int z = 0; z < MAXD; ++z)
-                    if (z < D && !((out >> z) & 1) && (worst < 0 || A[z] <= worstA)) {
-                        worst = z;
-                        worstA = A[z];
-                    }
-                out |= 1ull << worst;
-            }
-            sel = (D == 64 ? ~0ull : ((1ull << D) - 1)) & ~out;
-        }
-        if (tau >= 0.0f) {
+    if (kk == D) {
+        sel = full;
+    } else if (2 * kk <= D) {
+        // kk passes: the best remaining score, the nearer plane on equal scores
+        for (int j = 0; j < kk; ++j) {
+            int best = -1;
+            float bestA = 0.0f;
 #pragma unroll
             for (int z = 0; z < MAXD; ++z)
-                if (z < D && !(A[z] > tau)) sel &= ~(1ull << z);
+                if (z < D && !((sel >> z) & 1) && (best < 0 || A[z] > bestA)) {
+                    best = z;
+                    bestA = A[z];
+                }
+            sel |= 1ull << best;
         }
-        mask[p] = sel;
+    } else {
+        // D - kk passes removing the worst: the lowest score, the farther plane on ties
+        uint64_t out = 0;
+        for (int j = 0; j < D - kk; ++j) {
+            int worst = -1;
+            float worstA = 0.0f;
+#pragma unroll
+            for (int z = 0; z < MAXD; ++z)
+                if (z < D && !((out >> z) & 1) && (worst < 0 || A[z] <= worstA)) {
+                    worst = z;
+                    worstA = A[z];
+                }
+            out |= 1ull << worst;
+        }
+        sel = full & ~out;
     }
-    if (counts) {
-        const int64_t wblk = (int64_t)p >> 6;
-        for (int z = 0; z < D; ++z) {
-            const uint64_t bal = __ballot((sel >> z) & 1);
-            if ((threadIdx.x & 63) == 0 && wblk < nblk) counts[z * nblk + wblk] = __popcll(bal);
+    if (tau >= 0.0f) {
+#pragma unroll
+        for (int z = 0; z < MAXD; ++z)
+            if (z < D && !(A[z] > tau)) sel &= ~(1ull << z);
+    }
+    return sel;
+}
+
+// The transposed view of a 64-pixel block's masks: for every plane the wave ballot (bit
+// = pixel of the block) and its population count. Every lane of the wave must call it.
+__device__ __forceinline__ void emit_ballots(uint64_t sel, int D, int64_t wblk, int64_t nblk,
+                                             uint64_t* __restrict__ bal, int* __restrict__ cnt) {
+    for (int z = 0; z < D; ++z) {
+        const uint64_t b = __ballot((sel >> z) & 1);
+        if ((threadIdx.x & 63) == 0 && wblk < nblk) {
+            bal[z * nblk + wblk] = b;
+            cnt[z * nblk + wblk] = __popcll(b);
         }
     }
 }
 
-// Segmented exclusive scan, phase 1: each block scans 4096 consecutive counts in place
-// and writes its total.
+template <int DT, int MAXD>
+__global__ __launch_bounds__(256) void k_select(const void* __restrict__ mpi, int D, int HW, int k,
+                                                float tau, uint64_t* __restrict__ mask,
+                                                uint64_t* __restrict__ bal, int* __restrict__ cnt,
+                                                int64_t nblk) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t sel = 0;
+    if (p < HW) {
+        sel = select_bits<DT, MAXD>(mpi, D, HW, p, k, tau);
+        if (mask) mask[p] = sel;
+    }
+    if (bal) emit_ballots(sel, D, (int64_t)p >> 6, nblk, bal, cnt);
+}
+
+// Active-set structures from a caller's mask (NULL: every voxel); bits of a pixel beyond
+// its first kcap set bits are dropped.
+__global__ __launch_bounds__(256) void k_mask_ballot(const uint64_t* __restrict__ mask, int D, int HW,
+                                                     int kcap, uint64_t* __restrict__ bal,
+                                                     int* __restrict__ cnt, int64_t nblk) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t full = D == 64 ? ~0ull : ((1ull << D) - 1);
+    uint64_t sel = 0;
+    if (p < HW) {
+        sel = (mask ? mask[p] : full) & full;
+        if (__popcll(sel) > kcap) {
+            uint64_t kept = 0;
+            for (int j = 0; j < kcap; ++j) {
+                const uint64_t low = sel & (~sel + 1);
+                kept |= low;
+                sel &= sel - 1;
+            }
+            sel = kept;
+        }
+    }
+    emit_ballots(sel, D, (int64_t)p >> 6, nblk, bal, cnt);
+}
+
+// Segmented exclusive scan of the counts (plane-major), phase 1: each workgroup scans
+// kSeg consecutive entries in place and writes its total.
 constexpr int kSeg = kScanSeg;
 __global__ __launch_bounds__(256) void k_scan_seg(int* __restrict__ v, int64_t n,
                                                   int* __restrict__ seg_total) {
@@ -230,7 +288,7 @@ __global__ __launch_bounds__(256) void k_scan_seg(int* __restrict__ v, int64_t n
     for (int i = threadIdx.x; i < kSeg; i += 256) sv[i] = base + i < n ? v[base + i] : 0;
     __syncthreads();
     int s = 0;
-    for (int j = 0; j < 16; ++j) s += sv[threadIdx.x * 16 + j];
+    for (int j = 0; j < kSeg / 256; ++j) s += sv[threadIdx.x * (kSeg / 256) + j];
     ssum[threadIdx.x] = s;
     __syncthreads();
     for (int o = 1; o < 256; o <<= 1) {
@@ -240,9 +298,9 @@ __global__ __launch_bounds__(256) void k_scan_seg(int* __restrict__ v, int64_t n
         __syncthreads();
     }
     int run = ssum[threadIdx.x] - s;
-    for (int j = 0; j < 16; ++j) {
-        int c = sv[threadIdx.x * 16 + j];
-        sv[threadIdx.x * 16 + j] = run;
+    for (int j = 0; j < kSeg / 256; ++j) {
+        int c = sv[threadIdx.x * (kSeg / 256) + j];
+        sv[threadIdx.x * (kSeg / 256) + j] = run;
         run += c;
     }
     __syncthreads();
@@ -251,7 +309,7 @@ __global__ __launch_bounds__(256) void k_scan_seg(int* __restrict__ v, int64_t n
     if (threadIdx.x == 255) seg_total[blockIdx.x] = ssum[255];
 }
 
-// Phase 2 (one block): exclusive scan of the segment totals, plane offsets, |S|.
+// Phase 2 (one workgroup): exclusive scan of the segment totals; plane offsets and |S|.
 __global__ __launch_bounds__(1024) void k_scan_top(const int* __restrict__ v, int64_t nblk, int D,
                                                    int* __restrict__ seg, int nseg,
                                                    int* __restrict__ plane_off,
@@ -276,31 +334,39 @@ __global__ __launch_bounds__(1024) void k_scan_top(const int* __restrict__ v, in
         if (threadIdx.x == 1023) carry += sh[1023];
         __syncthreads();
     }
-    for (int z = threadIdx.x; z < D; z += 1024) {
-        const int64_t e = (int64_t)z * nblk;
-        plane_off[z] = v[e] + seg[e / kSeg];
+    if (plane_off) {
+        for (int z = threadIdx.x; z < D; z += 1024) {
+            const int64_t e = (int64_t)z * nblk;
+            plane_off[z] = v[e] + seg[e / kSeg];
+        }
     }
     if (threadIdx.x == 0) {
-        plane_off[D] = carry;
+        if (plane_off) plane_off[D] = carry;
         *n_active = carry;
     }
 }
 
-__global__ __launch_bounds__(256) void k_compact(const uint64_t* __restrict__ mask, int D, int HW,
-                                                 const int* __restrict__ off,
-                                                 const int* __restrict__ seg, int64_t nblk,
-                                                 int* __restrict__ ids, int cap) {
+// Wavefront compaction: each wave owns one 64-pixel block; for every plane its ballot
+// word gives the selected lanes and their rank (popcount below the lane), its scanned
+// offset the position of the block in the plane-major list. Also turns the offsets into
+// global positions in place, for the gradient kernels.
+__global__ __launch_bounds__(256) void k_compact(const uint64_t* __restrict__ bal, int* __restrict__ off,
+                                                 const int* __restrict__ seg, int D, int HW,
+                                                 int64_t nblk, int* __restrict__ ids, int64_t cap) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t bits = p < HW ? mask[p] : 0;
     const int64_t wblk = (int64_t)p >> 6;
-    const uint64_t lt = __lanemask_lt();
+    if (wblk >= nblk) return;   // whole waves only
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = (1ull << lane) - 1;
     for (int z = 0; z < D; ++z) {
-        const uint64_t bal = __ballot((bits >> z) & 1);
-        if ((bits >> z) & 1) {
-            const int64_t e = (int64_t)z * nblk + wblk;
-            const int pos = off[e] + seg[e / kSeg] + __popcll(bal & lt);
+        const int64_t e = (int64_t)z * nblk + wblk;
+        const uint64_t b = bal[e];
+        const int base = off[e] + seg[e / kSeg];
+        if ((b >> lane) & 1) {
+            const int64_t pos = (int64_t)base + __popcll(b & lt);
             if (pos < cap) ids[pos] = z * HW + p;
         }
+        if (lane == 0) off[e] = base;
     }
 }
 
@@ -368,18 +434,27 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
     if (threadIdx.x == 0) *out = (float)(sh[0] * scale);
 }
 
+// Position of voxel (z, p) in the plane-major compact order, or -1 if it is not in S.
+__device__ __forceinline__ int active_pos(const uint64_t* __restrict__ bal, const int* __restrict__ off,
+                                          int64_t nblk, int z, int p) {
+    const int64_t e = (int64_t)z * nblk + (p >> 6);
+    const uint64_t b = bal[e];
+    const int bit = p & 63;
+    if (!((b >> bit) & 1)) return -1;
+    return off[e] + __popcll(b & ((1ull << bit) - 1));
+}
+
 // ------------------------------------------------------------------------------------
-// gradient: forward scan, residual, back-to-front adjoint scan, restricted scatter
+// gradient, general warps: per-ray scans, atomic transposed-bilinear scatter into the
+// compact slots of S
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ void scatter_tap(float4* __restrict__ slots, const uint64_t* __restrict__ mask,
-                                            int kcap, int HW, uint64_t full, int z, int p, float w,
-                                            const float4& g) {
+__device__ __forceinline__ void scatter_tap(float4* __restrict__ slots, const uint64_t* __restrict__ bal,
+                                            const int* __restrict__ off, int64_t nblk, int z, int p,
+                                            float w, const float4& g) {
     if (w == 0.0f) return;
-    const uint64_t m = mask ? mask[p] : full;
-    if (!((m >> z) & 1)) return;
-    const int r = __popcll(m & ((1ull << z) - 1));
-    if (r >= kcap) return;
-    float* dst = reinterpret_cast<float*>(slots + (size_t)r * HW + p);
+    const int pos = active_pos(bal, off, nblk, z, p);
+    if (pos < 0) return;
+    float* dst = reinterpret_cast<float*>(slots + pos);
     atomicAdd(dst + 0, w * g.x);
     atomicAdd(dst + 1, w * g.y);
     atomicAdd(dst + 2, w * g.z);
@@ -391,7 +466,8 @@ __global__ __launch_bounds__(kBlock) void k_grad(const void* __restrict__ mpi, i
                                                  const hsgd_warp* __restrict__ warps,
                                                  const float* __restrict__ images,
                                                  const float* __restrict__ dimg,
-                                                 const uint64_t* __restrict__ mask, int kcap,
+                                                 const uint64_t* __restrict__ bal,
+                                                 const int* __restrict__ off, int64_t nblk,
                                                  float inv_n, float4* __restrict__ slots,
                                                  float* __restrict__ partials) {
     __shared__ hsgd_warp sw[MAXD];
@@ -402,7 +478,6 @@ __global__ __launch_bounds__(kBlock) void k_grad(const void* __restrict__ mpi, i
     const int x = blockIdx.x * kTileW + (threadIdx.x & 63);
     const int y = blockIdx.y * kTileH + (threadIdx.x >> 6);
     const int HW = H * W;
-    const uint64_t full = D == 64 ? ~0ull : ((1ull << D) - 1);
     float sq = 0.0f;
     if (x < W && y < H) {
         float Ts[MAXD];
@@ -421,7 +496,7 @@ __global__ __launch_bounds__(kBlock) void k_grad(const void* __restrict__ mpi, i
             }
         }
         const size_t pix = ((size_t)view * H + y) * W + x;
-        float g0, g1, g2;
+        float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
         if (images) {
             const float d0 = c0 - images[3 * pix + 0];
             const float d1 = c1 - images[3 * pix + 1];
@@ -454,10 +529,10 @@ __global__ __launch_bounds__(kBlock) void k_grad(const void* __restrict__ mpi, i
                 b0 = s.w * s.x + oa * b0;
                 b1 = s.w * s.y + oa * b1;
                 b2 = s.w * s.z + oa * b2;
-                scatter_tap(slots, mask, kcap, HW, full, z, tp.i00, tp.w00, gs);
-                scatter_tap(slots, mask, kcap, HW, full, z, tp.i10, tp.w10, gs);
-                scatter_tap(slots, mask, kcap, HW, full, z, tp.i01, tp.w01, gs);
-                scatter_tap(slots, mask, kcap, HW, full, z, tp.i11, tp.w11, gs);
+                scatter_tap(slots, bal, off, nblk, z, tp.i00, tp.w00, gs);
+                scatter_tap(slots, bal, off, nblk, z, tp.i10, tp.w10, gs);
+                scatter_tap(slots, bal, off, nblk, z, tp.i01, tp.w01, gs);
+                scatter_tap(slots, bal, off, nblk, z, tp.i11, tp.w11, gs);
             }
         }
     }
@@ -469,109 +544,194 @@ __global__ __launch_bounds__(kBlock) void k_grad(const void* __restrict__ mpi, i
 }
 
 // ------------------------------------------------------------------------------------
-// gradient for pure-translation warps: owner-computes, no atomics, deterministic
+// gradient, pure-translation warps: owner-computes, no atomics, deterministic
 //
-// A workgroup takes a 64 x 8 block of view rays: 63 x 7 "owner" rays plus one halo column
-// on the left and one halo row on top. For plane z every owner (x, y) also owns the
-// reference cell (x + ix_z, y + iy_z): with a translation the four rays whose bilinear
-// footprint covers that cell are the owner and its left, upper and upper-left neighbours,
-// all in the block. The per-ray adjoints are combined horizontally across lanes with DPP
-// and vertically across waves through LDS, and each owner writes its cell's gradient once
-// into the view's slice of the slot buffer (rank-major [view][kcap][H*W]).
+// A workgroup takes a 64 x 8 block of view rays: lane 0 and wave 0 are a halo column and
+// row, lane 63 only supplies the right-hand bilinear taps of lane 62, and the 62 x 7 rays
+// in between are "owners". For plane z every owner (x, y) also owns the reference cell
+// (x + ix_z, y + iy_z): with a translation, the four rays whose bilinear footprint covers
+// that cell are the owner and its left, upper and upper-left neighbours, all in the block.
+// Per-ray adjoints are combined across lanes with DPP and across waves through LDS, and
+// each owner writes its cell's gradient once, at the cell's position in S, into the
+// view's slice of the slot buffer. Which cells of a wave's row are in S, and where, comes
+// from the per-block ballot words and offsets (scalar loads); rows without selected cells
+// skip the adjoint.
 // ------------------------------------------------------------------------------------
-constexpr int kSX = kShiftOX + 1, kSY = kShiftOY + 1;  // rays per block (with halo)
-constexpr int kOX = kShiftOX, kOY = kShiftOY;          // owner rays (= owned cells) per block and plane
-static_assert(kSX == 64, "one wave per row of rays");
+constexpr int kSX = 64, kSY = kShiftOY + 1;
+constexpr int kOX = kShiftOX, kOY = kShiftOY;
+static_assert(kOX == kSX - 2, "lanes: halo, owners, tap supplier");
 
+// DPP wave shifts (bound_ctrl: a lane without a source reads 0)
 __device__ __forceinline__ float lane_from_next(float v) {   // lane i <- lane i+1 (63 <- 0)
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float lane_from_prev(float v) {   // lane i <- lane i-1 (0 <- 0)
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float4 lane_from_next4(float4 v) {
-    return make_float4(lane_from_next(v.x), lane_from_next(v.y), lane_from_next(v.z), lane_from_next(v.w));
-}
-__device__ __forceinline__ float4 lane_from_prev4(float4 v) {
-    return make_float4(lane_from_prev(v.x), lane_from_prev(v.y), lane_from_prev(v.z), lane_from_prev(v.w));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xF, 0xF, true));
 }
 
-// Block index -> tile index so that each XCD (blocks are dealt round-robin to the 8 XCDs)
-// works on a contiguous run of tiles: neighbouring tiles and the views of one tile share
-// MPI lines in that XCD's L2.
+// Block index -> tile index so that each XCD (workgroups are dealt round-robin to the 8
+// XCDs) works on a contiguous run of tiles: the views of one tile and neighbouring tiles
+// share MPI lines in that XCD's L2.
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
     const int q = nb >> 3, r = nb & 7, x = b & 7;
     return x * q + min(x, r) + (b >> 3);
 }
 
-struct ShiftRec {
+// Per-plane data of one wave, held one plane per lane (lane z = plane z) and fetched with
+// v_readlane inside the plane loops: the shift of the view's warp and which of the wave's
+// owned cells are in S (for its own row of cells and the row below).
+struct PlaneLanes {
     int ix, iy;
     float fx, fy;
+    uint32_t w0lo, w0hi, w1lo, w1hi;   // ballot words of the own row's first / second block
+    int o0, o1;                        // their offsets in S
+    int pfirst;                        // first pixel of the own row's first block
+    int flags;                         // bit 0: own row has selected cells; bit 1: row below
 };
 
-// Sample plane z at the ray (x, y) of this lane for a shift warp. All 64 lanes must call it
-// together (the right-hand taps come from the next lane through DPP).
-template <int DT>
-__device__ __forceinline__ float4 shift_sample(const void* __restrict__ mpi, int zbase, int H, int W,
-                                               int x, int y, const ShiftRec& sh, int lane) {
-    const int X0 = x + sh.ix, Y0 = y + sh.iy;
-    const bool y0ok = (unsigned)Y0 < (unsigned)H, y1ok = (unsigned)(Y0 + 1) < (unsigned)H;
-    const bool x0ok = (unsigned)X0 < (unsigned)W, x1ok = (unsigned)(X0 + 1) < (unsigned)W;
-    const int cx0 = min(max(X0, 0), W - 1);
-    const int r0 = zbase + min(max(Y0, 0), H - 1) * W;
-    const int r1 = zbase + min(max(Y0 + 1, 0), H - 1) * W;
-    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-    float4 t00 = (y0ok && x0ok) ? Vox<DT>::load(mpi, r0 + cx0) : zero;
-    float4 t01 = (y1ok && x0ok) ? Vox<DT>::load(mpi, r1 + cx0) : zero;
-    float4 t10 = lane_from_next4(t00);
-    float4 t11 = lane_from_next4(t01);
-    if (lane == kSX - 1) {
-        const int cx1 = min(max(X0 + 1, 0), W - 1);
-        t10 = (y0ok && x1ok) ? Vox<DT>::load(mpi, r0 + cx1) : zero;
-        t11 = (y1ok && x1ok) ? Vox<DT>::load(mpi, r1 + cx1) : zero;
+__device__ __forceinline__ int rl(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+__device__ __forceinline__ float rlf(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Selected cells among the 64 cells X0 .. X0+63 of row Y at plane z (0 <= X < W only).
+__device__ __forceinline__ void row_words(const uint64_t* __restrict__ bal, const int* __restrict__ off,
+                                          int nblk, int z, int Y, int X0, int H, int W, uint64_t& w0,
+                                          uint64_t& w1, int& o0, int& o1, int& pfirst, bool& any) {
+    w0 = w1 = 0;
+    o0 = o1 = 0;
+    pfirst = 0;
+    any = false;
+    const int xa = max(X0, 0), xb = min(X0 + 63, W - 1);
+    if ((unsigned)Y >= (unsigned)H || xa > xb) return;
+    const int pa = Y * W + xa, pb = Y * W + xb;
+    const int b0 = pa >> 6, b1 = pb >> 6;
+    const int e = z * nblk + b0;
+    pfirst = b0 << 6;
+    w0 = bal[e];
+    o0 = off[e];
+    if (b1 != b0) {
+        w1 = bal[e + 1];
+        o1 = off[e + 1];
     }
-    const float gx = 1.0f - sh.fx, gy = 1.0f - sh.fy;
+    const int lo = pa & 63;
+    uint64_t m0 = w0 >> lo, m1 = w1;
+    if (b1 == b0) {
+        const int n = pb - pa + 1;
+        m0 &= n >= 64 ? ~0ull : ((1ull << n) - 1);
+    } else {
+        const int hi = pb & 63;
+        m1 &= hi >= 63 ? ~0ull : ((1ull << (hi + 1)) - 1);
+    }
+    any = (m0 | m1) != 0;
+}
+
+// Bilinear sample of plane zbase for the ray of this lane: cx the clamped tap column, r0/r1
+// the (uniform) clamped tap rows, weights with out-of-plane taps already zeroed. All 64
+// lanes must call it together (the right-hand taps come from the next lane).
+template <int DT>
+__device__ __forceinline__ float4 shift_sample(const void* __restrict__ mpi, int r0, int r1, unsigned cx,
+                                               float w00, float w10, float w01, float w11) {
+    const float4 t00 = Vox<DT>::load_row(Vox<DT>::row_ptr(mpi, r0), cx);
+    const float4 t01 = Vox<DT>::load_row(Vox<DT>::row_ptr(mpi, r1), cx);
     float4 s;
-    s.x = (t00.x * gx + t10.x * sh.fx) * gy + (t01.x * gx + t11.x * sh.fx) * sh.fy;
-    s.y = (t00.y * gx + t10.y * sh.fx) * gy + (t01.y * gx + t11.y * sh.fx) * sh.fy;
-    s.z = (t00.z * gx + t10.z * sh.fx) * gy + (t01.z * gx + t11.z * sh.fx) * sh.fy;
-    s.w = (t00.w * gx + t10.w * sh.fx) * gy + (t01.w * gx + t11.w * sh.fx) * sh.fy;
+    s.x = w00 * t00.x + w10 * lane_from_next(t00.x) + w01 * t01.x + w11 * lane_from_next(t01.x);
+    s.y = w00 * t00.y + w10 * lane_from_next(t00.y) + w01 * t01.y + w11 * lane_from_next(t01.y);
+    s.z = w00 * t00.z + w10 * lane_from_next(t00.z) + w01 * t01.z + w11 * lane_from_next(t01.z);
+    s.w = w00 * t00.w + w10 * lane_from_next(t00.w) + w01 * t01.w + w11 * lane_from_next(t01.w);
     return s;
 }
 
-// REGS: keep every plane's sample in registers between the two scans (D <= 32); otherwise
-// sample again in the back-to-front scan.
+// Sampling of plane z for the lane's ray x at the wave's row y, from the plane's shift.
+struct Tap {
+    int r0, r1;
+    unsigned cx;
+    float w00, w10, w01, w11;
+};
+
+__device__ __forceinline__ Tap shift_tap(int zbase, int H, int W, int x, int y, int ix, int iy, float fx,
+                                         float fy, float live) {
+    Tap t;
+    const int Y0 = y + iy;
+    const bool y0ok = (unsigned)Y0 < (unsigned)H, y1ok = (unsigned)(Y0 + 1) < (unsigned)H;
+    t.r0 = zbase + min(max(Y0, 0), H - 1) * W;
+    t.r1 = zbase + min(max(Y0 + 1, 0), H - 1) * W;
+    const int X0 = x + ix;
+    t.cx = (unsigned)min(max(X0, 0), W - 1);
+    const bool x0ok = (unsigned)X0 < (unsigned)W, x1ok = (unsigned)(X0 + 1) < (unsigned)W;
+    const float gy = y0ok ? (1.0f - fy) * live : 0.0f, hy = y1ok ? fy * live : 0.0f;   // uniform
+    const float gx = 1.0f - fx;
+    t.w00 = x0ok ? gx * gy : 0.0f;
+    t.w10 = x1ok ? fx * gy : 0.0f;
+    t.w01 = x0ok ? gx * hy : 0.0f;
+    t.w11 = x1ok ? fx * hy : 0.0f;
+    return t;
+}
+
 template <int DT, int MAXD, bool REGS>
 __global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
     const void* __restrict__ mpi, int D, int H, int W, int N, const hsgd_warp* __restrict__ warps,
-    const float* __restrict__ images, const float* __restrict__ dimg, const uint64_t* __restrict__ mask,
-    int kcap, float inv_n, float4* __restrict__ slots, float* __restrict__ partials, int ntx, int nty) {
-    __shared__ ShiftRec s_sh[MAXD];
+    const float* __restrict__ images, const float* __restrict__ dimg, const uint64_t* __restrict__ bal,
+    const int* __restrict__ off, int nblk, int64_t cap, float inv_n, float4* __restrict__ slots,
+    float* __restrict__ partials, int ntx, int nty) {
     __shared__ float4 s_h[2][kSX * kSY];
     __shared__ float sred[kSX * kSY / 64];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int view = tile % N;
     const int t2 = tile / N;
     const int tx = t2 % ntx, ty = t2 / ntx;
-    for (int z = threadIdx.x; z < D; z += blockDim.x) {
-        const hsgd_warp& w = warps[(size_t)view * D + z];
-        s_sh[z] = ShiftRec{w.ix, w.iy, w.fx, w.fy};
-    }
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int x = tx * kOX - 1 + lane, y = ty * kOY - 1 + wv;
-    const bool valid = (unsigned)x < (unsigned)W && (unsigned)y < (unsigned)H;
-    const bool owner = lane >= 1 && wv >= 1;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int xl = tx * kOX - 1;                 // x of lane 0
+    const int x = xl + lane, y = ty * kOY - 1 + wv;
+    const bool ray = lane < kSX - 1 && (unsigned)x < (unsigned)W && (unsigned)y < (unsigned)H;
+    const bool owner = lane >= 1 && lane < kSX - 1 && wv >= 1;
     const int HW = H * W;
-    const uint64_t full = D == 64 ? ~0ull : ((1ull << D) - 1);
 
+    // prologue: lane z < D gathers plane z's shift and this wave's selection words
+    PlaneLanes pl;
+    {
+        pl.ix = pl.iy = 0;
+        pl.fx = pl.fy = 0.0f;
+        uint64_t w0 = 0, w1 = 0;
+        int o0 = 0, o1 = 0, pf = 0, fl = 0;
+        if (lane < D) {
+            const hsgd_warp& w = warps[(size_t)view * D + lane];
+            pl.ix = w.ix;
+            pl.iy = w.iy;
+            pl.fx = w.fx;
+            pl.fy = w.fy;
+            bool any_own, any_below;
+            uint64_t u0, u1;
+            int q0, q1, qf;
+            row_words(bal, off, nblk, lane, y + pl.iy + 1, xl + pl.ix, H, W, u0, u1, q0, q1, qf, any_below);
+            row_words(bal, off, nblk, lane, y + pl.iy, xl + pl.ix, H, W, w0, w1, o0, o1, pf, any_own);
+            fl = (any_own && wv >= 1 ? 1 : 0) | (any_below && wv + 1 < kSY ? 2 : 0);
+        }
+        pl.w0lo = (uint32_t)w0;
+        pl.w0hi = (uint32_t)(w0 >> 32);
+        pl.w1lo = (uint32_t)w1;
+        pl.w1hi = (uint32_t)(w1 >> 32);
+        pl.o0 = o0;
+        pl.o1 = o1;
+        pl.pfirst = pf;
+        pl.flags = fl;
+    }
+
+    // Plane loops run over MAXD planes without branches (so loads of later planes can be
+    // issued early); planes z >= D sample plane D-1 with zero weight: a transparent plane.
     float4 smp[REGS ? MAXD : 1];
     float Ts[MAXD];
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
 #pragma unroll
     for (int z = 0; z < MAXD; ++z) {
-        if (z < D) {
-            const float4 s = shift_sample<DT>(mpi, z * HW, H, W, x, y, s_sh[z], lane);
+        // without REGS (64 planes) the per-plane branch stays: it keeps the scheduler from
+        // hoisting every plane's loads at once
+        if (REGS || z < D) {
+            const float live = z < D ? 1.0f : 0.0f;
+            const Tap tp = shift_tap(min(z, D - 1) * HW, H, W, x, y, rl(pl.ix, z), rl(pl.iy, z), rlf(pl.fx, z),
+                                     rlf(pl.fy, z), live);
+            const float4 s = shift_sample<DT>(mpi, tp.r0, tp.r1, tp.cx, tp.w00, tp.w10, tp.w01, tp.w11);
             if (REGS) smp[z] = s;
             Ts[z] = T;
             const float wgt = T * s.w;
@@ -582,7 +742,7 @@ __global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
         }
     }
     float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, sq = 0.0f;
-    if (valid) {
+    if (ray) {
         const size_t pix = ((size_t)view * H + y) * W + x;
         if (images) {
             const float d0 = c0 - images[3 * pix + 0];
@@ -600,54 +760,63 @@ __global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
         }
     }
     float b0 = 0.0f, b1 = 0.0f, b2 = 0.0f;   // composite behind plane z
-    float4* vslots = slots + (size_t)view * kcap * HW;
+    float4* __restrict__ vslots = slots + (size_t)view * cap;
 #pragma unroll
     for (int zz = 0; zz < MAXD; ++zz) {
         const int z = MAXD - 1 - zz;
-        if (z < D) {
-            const ShiftRec sh = s_sh[z];
-            const float4 s = REGS ? smp[REGS ? z : 0] : shift_sample<DT>(mpi, z * HW, H, W, x, y, sh, lane);
-            const float Tz = Ts[z];
-            const float ca = s.w * Tz;
-            float4 a;
-            a.x = g0 * ca;
-            a.y = g1 * ca;
-            a.z = g2 * ca;
-            a.w = Tz * (g0 * (s.x - b0) + g1 * (s.y - b1) + g2 * (s.z - b2));
+        if (REGS || z < D) {
+            const int ix = rl(pl.ix, z), iy = rl(pl.iy, z);
+            const float fx = rlf(pl.fx, z), fy = rlf(pl.fy, z);
+            const int flags = rl(pl.flags, z);   // 0 for planes z >= D
+            float4 s;
+            if (REGS) {
+                s = smp[REGS ? z : 0];
+            } else {
+                const Tap tp = shift_tap(min(z, D - 1) * HW, H, W, x, y, ix, iy, fx, fy, z < D ? 1.0f : 0.0f);
+                s = shift_sample<DT>(mpi, tp.r0, tp.r1, tp.cx, tp.w00, tp.w10, tp.w01, tp.w11);
+            }
+            float4* buf = s_h[z & 1];
+            float4 h;
+            if (flags) {
+                const float Tz = Ts[z];
+                const float ca = s.w * Tz;
+                float4 a;
+                a.x = g0 * ca;
+                a.y = g1 * ca;
+                a.z = g2 * ca;
+                a.w = Tz * (g0 * (s.x - b0) + g1 * (s.y - b1) + g2 * (s.z - b2));
+                // horizontal half of the transposed bilinear: this ray (1 - fx) and the
+                // ray to the left (fx) both touch the owned cell's row
+                const float gx = 1.0f - fx;
+                h.x = a.x * gx + lane_from_prev(a.x) * fx;
+                h.y = a.y * gx + lane_from_prev(a.y) * fx;
+                h.z = a.z * gx + lane_from_prev(a.z) * fx;
+                h.w = a.w * gx + lane_from_prev(a.w) * fx;
+                buf[threadIdx.x] = h;
+            }
             const float oa = 1.0f - s.w;
             b0 = s.w * s.x + oa * b0;
             b1 = s.w * s.y + oa * b1;
             b2 = s.w * s.z + oa * b2;
-            // horizontal half of the transposed bilinear: this ray (weight 1 - fx) and the
-            // ray to its left (weight fx) both touch the owned cell's row
-            const float4 ap = lane_from_prev4(a);
-            const float gx = 1.0f - sh.fx;
-            float4 h;
-            h.x = a.x * gx + ap.x * sh.fx;
-            h.y = a.y * gx + ap.y * sh.fx;
-            h.z = a.z * gx + ap.z * sh.fx;
-            h.w = a.w * gx + ap.w * sh.fx;
-            float4* buf = s_h[z & 1];
-            buf[threadIdx.x] = h;
             __syncthreads();
-            if (owner) {
-                const int X = x + sh.ix, Y = y + sh.iy;
-                if ((unsigned)X < (unsigned)W && (unsigned)Y < (unsigned)H) {
-                    const int p = Y * W + X;
-                    const uint64_t m = mask ? mask[p] : full;
-                    if ((m >> z) & 1) {
-                        const int r = __popcll(m & ((1ull << z) - 1));
-                        if (r < kcap) {
-                            const float4 hu = buf[threadIdx.x - 64];   // the row above
-                            const float gy = 1.0f - sh.fy;
-                            float4 c;
-                            c.x = h.x * gy + hu.x * sh.fy;
-                            c.y = h.y * gy + hu.y * sh.fy;
-                            c.z = h.z * gy + hu.z * sh.fy;
-                            c.w = h.w * gy + hu.w * sh.fy;
-                            vslots[(size_t)r * HW + p] = c;
-                        }
-                    }
+            if (flags & 1) {
+                const int Y = y + iy;
+                const int X = xl + ix + lane;
+                const int j = Y * W + X - rl(pl.pfirst, z);   // 0..127 inside the row
+                const uint32_t lo = (uint32_t)(j < 64 ? rl(pl.w0lo, z) : rl(pl.w1lo, z));
+                const uint32_t hi = (uint32_t)(j < 64 ? rl(pl.w0hi, z) : rl(pl.w1hi, z));
+                const uint64_t word = ((uint64_t)hi << 32) | lo;
+                const int bit = j & 63;
+                if (owner && (unsigned)X < (unsigned)W && ((word >> bit) & 1)) {
+                    const int pos = (j < 64 ? rl(pl.o0, z) : rl(pl.o1, z)) + __popcll(word & ((1ull << bit) - 1));
+                    const float4 hu = buf[threadIdx.x - 64];   // the row above
+                    const float gy = 1.0f - fy;
+                    float4 c;
+                    c.x = h.x * gy + hu.x * fy;
+                    c.y = h.y * gy + hu.y * fy;
+                    c.z = h.z * gy + hu.z * fy;
+                    c.w = h.w * gy + hu.w * fy;
+                    if (pos < cap) vslots[pos] = c;
                 }
             }
         }
@@ -664,69 +833,49 @@ __global__ __launch_bounds__(256) void k_fill_zero(float4* __restrict__ p, int64
     for (int64_t j = i; j < n; j += stride) p[j] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-// Sum the per-view gradient slices of every selected voxel, then apply the clamped descent
-// step in place and/or write the dense-masked gradient. With shift warps, a view's slice
-// holds a voxel only if the voxel lies in that view's owner coverage; outside it the view
-// contributes nothing (no ray of the view reaches the voxel) and the slot is not read.
+// One thread per voxel of S (compact order): sum the view slices, apply the clamped
+// descent step in place and/or write the gradient out. With shift warps, view v holds the
+// voxel only if the voxel lies in v's owner coverage; outside it no ray of v reaches the
+// voxel and the slot is not read.
 template <int DT, bool SHIFT>
 __global__ __launch_bounds__(256) void k_update(void* __restrict__ mpi, int D, int H, int W,
-                                                const uint64_t* __restrict__ mask, int kcap,
-                                                const float4* __restrict__ slots, int nslices,
-                                                const hsgd_warp* __restrict__ warps, int cover_w,
-                                                int cover_h, float lr_rgb, float lr_a, int do_update,
-                                                float4* __restrict__ grad_out) {
+                                                const int* __restrict__ ids, const int* __restrict__ nact,
+                                                int64_t cap, const float4* __restrict__ slots,
+                                                int nslices, const hsgd_warp* __restrict__ warps,
+                                                int cover_w, int cover_h, float lr_rgb, float lr_a,
+                                                int do_update, float4* __restrict__ grad_out) {
     extern __shared__ int2 s_off[];   // [nslices][D] (ix, iy) when SHIFT
     if (SHIFT) {
         for (int i = threadIdx.x; i < nslices * D; i += blockDim.x) s_off[i] = make_int2(warps[i].ix, warps[i].iy);
         __syncthreads();
     }
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= *nact || i >= cap) return;
     const int HW = H * W;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= HW) return;
-    const int X = p % W, Y = p / W;
-    const uint64_t full = D == 64 ? ~0ull : ((1ull << D) - 1);
-    const uint64_t m = mask ? mask[p] : full;
-    auto grad_of = [&](int z, int r) {
-        float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int v = 0; v < nslices; ++v) {
-            if (SHIFT) {
-                const int2 o = s_off[v * D + z];
-                const int cx = X - o.x, cy = Y - o.y;
-                if ((unsigned)cx >= (unsigned)cover_w || (unsigned)cy >= (unsigned)cover_h) continue;
-            }
-            const float4 t = slots[((size_t)v * kcap + r) * HW + p];
-            g.x += t.x;
-            g.y += t.y;
-            g.z += t.z;
-            g.w += t.w;
+    const int id = ids[i];
+    const int z = id / HW;
+    const int p = id - z * HW;
+    const int Y = p / W, X = p - Y * W;
+    float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int v = 0; v < nslices; ++v) {
+        if (SHIFT) {
+            const int2 o = s_off[v * D + z];
+            if ((unsigned)(X - o.x) >= (unsigned)cover_w || (unsigned)(Y - o.y) >= (unsigned)cover_h) continue;
         }
-        return g;
-    };
-    if (grad_out) {
-        int r = 0;
-        for (int z = 0; z < D; ++z) {
-            float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
-            if ((m >> z) & 1) {
-                if (r < kcap) g = grad_of(z, r);
-                ++r;
-            }
-            grad_out[(size_t)z * HW + p] = g;
-        }
+        const float4 t = slots[(size_t)v * cap + i];
+        g.x += t.x;
+        g.y += t.y;
+        g.z += t.z;
+        g.w += t.w;
     }
+    if (grad_out) grad_out[id] = g;
     if (do_update) {
-        uint64_t b = m;
-        int r = 0;
-        while (b && r < kcap) {
-            const int z = __ffsll((unsigned long long)b) - 1;
-            b &= b - 1;
-            const float4 g = grad_of(z, r++);
-            float4 v = Vox<DT>::load(mpi, z * HW + p);
-            v.x = fminf(fmaxf(v.x - lr_rgb * g.x, 0.0f), 1.0f);
-            v.y = fminf(fmaxf(v.y - lr_rgb * g.y, 0.0f), 1.0f);
-            v.z = fminf(fmaxf(v.z - lr_rgb * g.z, 0.0f), 1.0f);
-            v.w = fminf(fmaxf(v.w - lr_a * g.w, 0.0f), 1.0f);
-            Vox<DT>::store(mpi, z * HW + p, v);
-        }
+        float4 v = Vox<DT>::load(mpi, id);
+        v.x = fminf(fmaxf(v.x - lr_rgb * g.x, 0.0f), 1.0f);
+        v.y = fminf(fmaxf(v.y - lr_rgb * g.y, 0.0f), 1.0f);
+        v.z = fminf(fmaxf(v.z - lr_rgb * g.z, 0.0f), 1.0f);
+        v.w = fminf(fmaxf(v.w - lr_a * g.w, 0.0f), 1.0f);
+        Vox<DT>::store(mpi, id, v);
     }
 }
 
@@ -787,16 +936,16 @@ __global__ __launch_bounds__(256) void k_convert(const void* __restrict__ src, v
 
 int maxd_class(int D) { return D <= 8 ? 8 : D <= 16 ? 16 : D <= 32 ? 32 : 64; }
 
-#define HSGD_DISPATCH_D(D, BODY)                 \
-    switch (maxd_class(D)) {                     \
+#define HSGD_DISPATCH_D(D, BODY)                         \
+    switch (maxd_class(D)) {                             \
         case 8: { constexpr int MD = 8; BODY; } break;   \
         case 16: { constexpr int MD = 16; BODY; } break; \
         case 32: { constexpr int MD = 32; BODY; } break; \
         default: { constexpr int MD = 64; BODY; } break; \
     }
 
-#define HSGD_DISPATCH_T(dt, BODY)                                            \
-    if ((dt) == HSGD_FP32) { constexpr int DT = HSGD_FP32; BODY; }            \
+#define HSGD_DISPATCH_T(dt, BODY)                                  \
+    if ((dt) == HSGD_FP32) { constexpr int DT = HSGD_FP32; BODY; } \
     else { constexpr int DT = HSGD_BF16; BODY; }
 
 }  // namespace
@@ -804,31 +953,45 @@ int maxd_class(int D) { return D <= 8 ? 8 : D <= 16 ? 16 : D <= 32 ? 32 : 64; }
 // ------------------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------------------
-int launch_select(const hsgd_mpi& m, int k, float tau, uint64_t* mask, int32_t* ids, int cap,
-                  int32_t* plane_off, int32_t* n_active, void* ws, hipStream_t s) {
+static int launch_scan_compact(const ActiveSet& as, int D, int HW, int* plane_off, hipStream_t s) {
+    const int64_t n = (int64_t)D * as.nblk;
+    {
+        ProfScope ps(HSGD_K_SCAN, s);
+        hipLaunchKernelGGL(k_scan_seg, dim3((unsigned)as.nseg), dim3(256), 0, s, as.off, n, as.seg);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, as.off, as.nblk, D, as.seg, (int)as.nseg,
+                           plane_off, as.nact);
+    }
+    ProfScope ps(HSGD_K_COMPACT, s);
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)ceil_div(as.nblk * 64, 256)), dim3(256), 0, s, as.bal, as.off,
+                       as.seg, D, HW, as.nblk, as.ids, as.cap);
+    return (int)hipGetLastError();
+}
+
+int launch_select(const hsgd_mpi& m, int k, float tau, uint64_t* mask, const ActiveSet* as,
+                  int32_t* plane_off, hipStream_t s) {
     const int HW = m.H * m.W;
-    const SelectWs L = select_ws(m.D, m.H, m.W);
-    int* counts = ids ? reinterpret_cast<int*>((char*)ws + L.counts_off) : nullptr;
     const dim3 grid((unsigned)ceil_div(HW, 256));
     {
         ProfScope ps(HSGD_K_SELECT, s);
         HSGD_DISPATCH_T(m.dtype, HSGD_DISPATCH_D(m.D, hipLaunchKernelGGL((k_select<DT, MD>), grid, dim3(256), 0, s,
-                                                                        m.rgba, m.D, HW, k, tau, mask, counts, L.nblk)));
+                                                                        m.rgba, m.D, HW, k, tau, mask,
+                                                                        as ? as->bal : nullptr,
+                                                                        as ? as->off : nullptr,
+                                                                        as ? as->nblk : (int64_t)0)));
     }
-    if (ids) {
-        const int64_t n = (int64_t)m.D * L.nblk;
-        const int nseg = (int)L.nseg;
-        int* seg = reinterpret_cast<int*>((char*)ws + L.seg_off);
-        {
-            ProfScope ps(HSGD_K_SCAN, s);
-            hipLaunchKernelGGL(k_scan_seg, dim3(nseg), dim3(256), 0, s, counts, n, seg);
-            hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, counts, L.nblk, m.D, seg, nseg,
-                               plane_off, n_active);
-        }
-        ProfScope ps(HSGD_K_COMPACT, s);
-        hipLaunchKernelGGL(k_compact, grid, dim3(256), 0, s, mask, m.D, HW, counts, seg, L.nblk, ids, cap);
+    if (!as) return (int)hipGetLastError();
+    return launch_scan_compact(*as, m.D, HW, plane_off, s);
+}
+
+int launch_active_from_mask(int D, int H, int W, const uint64_t* mask, int kcap, const ActiveSet& as,
+                            hipStream_t s) {
+    const int HW = H * W;
+    {
+        ProfScope ps(HSGD_K_SELECT, s);
+        hipLaunchKernelGGL(k_mask_ballot, dim3((unsigned)ceil_div(HW, 256)), dim3(256), 0, s, mask, D, HW, kcap,
+                           as.bal, as.off, as.nblk);
     }
-    return (int)hipGetLastError();
+    return launch_scan_compact(as, D, HW, nullptr, s);
 }
 
 int launch_render(const hsgd_mpi& m, const hsgd_views& v, float* out_rgb, float* out_loss,
@@ -848,17 +1011,20 @@ int launch_render(const hsgd_mpi& m, const hsgd_views& v, float* out_rgb, float*
     return (int)hipGetLastError();
 }
 
-int launch_grad_step(const hsgd_mpi& m, const hsgd_views& v, const uint64_t* mask, int kcap,
-                     const float* dimg, float lr_rgb, float lr_alpha, float* grad_out,
-                     float* out_loss, void* ws, hipStream_t s) {
+int launch_grad_step(const hsgd_mpi& m, const hsgd_views& v, const ActiveSet& as, const float* dimg,
+                     float lr_rgb, float lr_alpha, float* grad_out, float* out_loss, float4* slots,
+                     float* partials, hipStream_t s) {
     const int HW = m.H * m.W;
-    const GradWs L = grad_ws(m.D, m.H, m.W, v.N, kcap);
-    float4* slots = reinterpret_cast<float4*>((char*)ws + L.slots_off);
-    float* partials = reinterpret_cast<float*>((char*)ws + L.partial_off);
     const float inv_n = 1.0f / (float)v.N;
     const bool shift = (v.flags & HSGD_VIEWS_SHIFT_ONLY) != 0;
     int64_t nparts;
     int cover_w = 0, cover_h = 0;
+    if (grad_out) {
+        ProfScope ps(HSGD_K_FILL, s);
+        const int64_t n = (int64_t)m.D * HW;
+        hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)std::min<int64_t>(ceil_div(n, 256), 8192)), dim3(256), 0, s,
+                           reinterpret_cast<float4*>(grad_out), n);
+    }
     if (shift) {
         const int ntx = (int)ceil_div(m.W + 1, kOX), nty = (int)ceil_div(m.H + 1, kOY);
         cover_w = ntx * kOX;
@@ -866,48 +1032,45 @@ int launch_grad_step(const hsgd_mpi& m, const hsgd_views& v, const uint64_t* mas
         nparts = (int64_t)ntx * nty * v.N;
         const dim3 grid((unsigned)nparts);
         ProfScope ps(HSGD_K_GRAD, s);
+#define HSGD_SHIFT_LAUNCH(MD, REGS)                                                                         \
+    hipLaunchKernelGGL((k_grad_shift<DT, MD, REGS>), grid, dim3(kSX * kSY), 0, s, m.rgba, m.D, m.H, m.W, v.N, \
+                       v.warps, v.images, dimg, as.bal, as.off, as.nblk, as.cap, inv_n, slots,               \
+                       out_loss ? partials : nullptr, ntx, nty)
         HSGD_DISPATCH_T(m.dtype, switch (maxd_class(m.D)) {
-            case 8: hipLaunchKernelGGL((k_grad_shift<DT, 8, true>), grid, dim3(kSX * kSY), 0, s, m.rgba, m.D, m.H, m.W,
-                                       v.N, v.warps, v.images, dimg, mask, kcap, inv_n, slots,
-                                       out_loss ? partials : nullptr, ntx, nty); break;
-            case 16: hipLaunchKernelGGL((k_grad_shift<DT, 16, true>), grid, dim3(kSX * kSY), 0, s, m.rgba, m.D, m.H, m.W,
-                                        v.N, v.warps, v.images, dimg, mask, kcap, inv_n, slots,
-                                        out_loss ? partials : nullptr, ntx, nty); break;
-            case 32: hipLaunchKernelGGL((k_grad_shift<DT, 32, true>), grid, dim3(kSX * kSY), 0, s, m.rgba, m.D, m.H, m.W,
-                                        v.N, v.warps, v.images, dimg, mask, kcap, inv_n, slots,
-                                        out_loss ? partials : nullptr, ntx, nty); break;
-            default: hipLaunchKernelGGL((k_grad_shift<DT, 64, false>), grid, dim3(kSX * kSY), 0, s, m.rgba, m.D, m.H, m.W,
-                                        v.N, v.warps, v.images, dimg, mask, kcap, inv_n, slots,
-                                        out_loss ? partials : nullptr, ntx, nty); break;
+            case 8: HSGD_SHIFT_LAUNCH(8, true); break;
+            case 16: HSGD_SHIFT_LAUNCH(16, true); break;
+            case 32: HSGD_SHIFT_LAUNCH(32, true); break;
+            default: HSGD_SHIFT_LAUNCH(64, false); break;
         });
+#undef HSGD_SHIFT_LAUNCH
     } else {
-        const int64_t nslots = (int64_t)kcap * HW;
-        const int fill_blocks = (int)std::min<int64_t>(ceil_div(nslots, 256), 4096);
         {
             ProfScope ps(HSGD_K_FILL, s);
-            hipLaunchKernelGGL(k_fill_zero, dim3(fill_blocks), dim3(256), 0, s, slots, nslots);
+            hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)std::min<int64_t>(ceil_div(as.cap, 256), 8192)), dim3(256),
+                               0, s, slots, as.cap);
         }
         const dim3 grid((unsigned)ceil_div(m.W, kTileW), (unsigned)ceil_div(m.H, kTileH), (unsigned)v.N);
         nparts = (int64_t)grid.x * grid.y * grid.z;
         ProfScope ps(HSGD_K_GRAD, s);
         HSGD_DISPATCH_T(m.dtype, HSGD_DISPATCH_D(m.D, hipLaunchKernelGGL((k_grad<DT, MD>), grid, dim3(kBlock), 0, s,
                                                                         m.rgba, m.D, m.H, m.W, v.warps, v.images, dimg,
-                                                                        mask, kcap, inv_n, slots,
+                                                                        as.bal, as.off, as.nblk, inv_n, slots,
                                                                         out_loss ? partials : nullptr)));
     }
     const int do_update = (lr_rgb != 0.0f || lr_alpha != 0.0f) ? 1 : 0;
-    {
+    if (do_update || grad_out) {
         ProfScope ps(HSGD_K_UPDATE, s);
-        const dim3 grid((unsigned)ceil_div(HW, 256));
+        const dim3 grid((unsigned)ceil_div(as.cap, 256));
         if (shift) {
             const size_t lds = sizeof(int2) * (size_t)v.N * m.D;
             HSGD_DISPATCH_T(m.dtype, hipLaunchKernelGGL((k_update<DT, true>), grid, dim3(256), lds, s, m.rgba, m.D, m.H,
-                                                        m.W, mask, kcap, slots, v.N, v.warps, cover_w, cover_h, lr_rgb,
-                                                        lr_alpha, do_update, reinterpret_cast<float4*>(grad_out)));
+                                                        m.W, as.ids, as.nact, as.cap, slots, v.N, v.warps, cover_w,
+                                                        cover_h, lr_rgb, lr_alpha, do_update,
+                                                        reinterpret_cast<float4*>(grad_out)));
         } else {
             HSGD_DISPATCH_T(m.dtype, hipLaunchKernelGGL((k_update<DT, false>), grid, dim3(256), 0, s, m.rgba, m.D, m.H,
-                                                        m.W, mask, kcap, slots, 1, v.warps, 0, 0, lr_rgb, lr_alpha,
-                                                        do_update, reinterpret_cast<float4*>(grad_out)));
+                                                        m.W, as.ids, as.nact, as.cap, slots, 1, v.warps, 0, 0, lr_rgb,
+                                                        lr_alpha, do_update, reinterpret_cast<float4*>(grad_out)));
         }
     }
     if (out_loss) {
