@@ -73,12 +73,9 @@ hsgd_status hsgd_grad_step(hsgd_mpi* m, const hsgd_views* v, const uint64_t* mas
     const GradWs L = grad_ws(m->D, m->H, m->W, v->N, kcap);
     st = check_ws(ws, ws_bytes, L.bytes);
     if (st) return st;
-    const ActiveSet as = active_at(ws, L.act);
-    int e = launch_active_from_mask(m->D, m->H, m->W, mask, kcap, as, stream);
-    if (e) return hip_status(e, fn);
     float4* slots = reinterpret_cast<float4*>((char*)ws + L.slots_off);
     float* partials = reinterpret_cast<float*>((char*)ws + L.partial_off);
-    return hip_status(launch_grad_step(*m, *v, as, dimg, lr_rgb, lr_alpha, grad_out, out_loss, slots,
+    return hip_status(launch_grad_step(*m, *v, mask, kcap, dimg, lr_rgb, lr_alpha, grad_out, out_loss, slots,
                                        partials, stream), fn);
 }
 
@@ -165,7 +162,8 @@ hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
         if (e) return hip_status(e, fn);
         img[l] = dst;
     }
-    // one workspace region sized for the finest level serves every level
+    // one mask and one workspace region sized for the finest level serve every level
+    uint64_t* mask = reinterpret_cast<uint64_t*>((char*)ws + R.mask_off);
     char* inner = (char*)ws + R.inner_off;
     int it_global = 0;
     for (int l = 0; l < L; ++l) {
@@ -176,13 +174,12 @@ hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
         hsgd_views v = views[l];
         v.images = img[l];
         const GradWs G = grad_ws(levels[l].D, levels[l].H, levels[l].W, N, sel.k);
-        const ActiveSet as = active_at(inner, G.act);
         float4* slots = reinterpret_cast<float4*>(inner + G.slots_off);
         float* partials = reinterpret_cast<float*>(inner + G.partial_off);
         for (int it = 0; it < iters[l]; ++it, ++it_global) {
-            int e = launch_select(levels[l], sel.k, sel.tau, nullptr, &as, nullptr, stream);
+            int e = launch_select(levels[l], sel.k, sel.tau, mask, nullptr, nullptr, stream);
             if (e) return hip_status(e, fn);
-            e = launch_grad_step(levels[l], v, as, nullptr, lr_rgb, lr_alpha, nullptr,
+            e = launch_grad_step(levels[l], v, mask, sel.k, nullptr, lr_rgb, lr_alpha, nullptr,
                                  loss_log ? loss_log + it_global : nullptr, slots, partials, stream);
             if (e) return hip_status(e, fn);
         }

@@ -110,11 +110,11 @@ RenderWs render_ws(int H, int W, int N) {
 }
 
 GradWs grad_ws(int D, int H, int W, int N, int kcap) {
+    (void)D;
     GradWs w{};
     const int64_t cap = (int64_t)kcap * H * W;
-    w.act = active_ws(D, H, W, cap, true);
-    w.slots_off = w.act.bytes;
-    w.partial_off = w.slots_off + align_up(sizeof(float) * 4 * (size_t)N * cap);
+    w.slots_off = 0;
+    w.partial_off = align_up(sizeof(float) * 4 * (size_t)N * cap);
     const int64_t general = ceil_div(W, kTileW) * ceil_div(H, kTileH) * N;
     const int64_t shift = ceil_div(W + 1, kShiftOX) * ceil_div(H + 1, kShiftOY) * N;
     w.nparts = general > shift ? general : shift;
@@ -130,6 +130,8 @@ RefineWs refine_ws(int D, int H, int W, int N, int k, int L) {
         w.pyr_off[l] = off;
         off += align_up(sizeof(float) * 3 * (size_t)N * (H / s) * (W / s));
     }
+    w.mask_off = off;
+    off += align_up(sizeof(uint64_t) * (size_t)H * W);
     w.inner_off = off;
     off += grad_ws(D, H, W, N, k).bytes;
     w.bytes = off;

@@ -5,7 +5,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
-#include "../../include/hsgd.h"
+#include "hsgd.h"
 
 namespace hsgd {
 
@@ -64,20 +64,19 @@ struct RenderWs {
 };
 RenderWs render_ws(int H, int W, int N);
 
-// grad_step: the active set (capacity kcap*H*W), one FP32 gradient slice per view over S
-// ([N][cap] float4) and the loss partials.
+// grad_step: FP32 gradient slots, one rank-major slice [kcap][H*W] of float4 per view,
+// and the loss partials.
 struct GradWs {
-    ActiveLayout act;
     size_t slots_off, partial_off, bytes;
     int64_t nparts;
 };
 GradWs grad_ws(int D, int H, int W, int N, int kcap);
 
-// refine: the target pyramid below the finest level, then the finest level's grad_step
-// workspace (reused by every level).
+// refine: the target pyramid below the finest level, the plane mask, then the finest
+// level's grad_step workspace (reused by every level).
 struct RefineWs {
     size_t pyr_off[16];
-    size_t inner_off, bytes;
+    size_t mask_off, inner_off, bytes;
 };
 RefineWs refine_ws(int D, int H, int W, int N, int k, int L);
 
@@ -105,14 +104,12 @@ class ProfScope {
 // select: mask (nullable) and, when as != NULL, the active set (plane_off nullable).
 int launch_select(const hsgd_mpi& m, int k, float tau, uint64_t* mask, const ActiveSet* as,
                   int32_t* plane_off, hipStream_t s);
-// the active set of a caller's mask (NULL mask: every voxel), first kcap bits per pixel.
-int launch_active_from_mask(int D, int H, int W, const uint64_t* mask, int kcap,
-                            const ActiveSet& as, hipStream_t s);
 int launch_render(const hsgd_mpi& m, const hsgd_views& v, float* out_rgb, float* out_loss,
                   void* ws, hipStream_t s);
-int launch_grad_step(const hsgd_mpi& m, const hsgd_views& v, const ActiveSet& as, const float* dimg,
-                     float lr_rgb, float lr_alpha, float* grad_out, float* out_loss, float4* slots,
-                     float* partials, hipStream_t s);
+// mask NULL: every voxel selected (kcap = D); otherwise the first kcap planes of each pixel.
+int launch_grad_step(const hsgd_mpi& m, const hsgd_views& v, const uint64_t* mask, int kcap,
+                     const float* dimg, float lr_rgb, float lr_alpha, float* grad_out, float* out_loss,
+                     float4* slots, float* partials, hipStream_t s);
 int launch_upsample(const hsgd_mpi& coarse, const hsgd_mpi& fine, hipStream_t s);
 int launch_downsample(const float* img, int N, int H, int W, float* out, hipStream_t s);
 int launch_convert(const void* src, int sdt, void* dst, int ddt, size_t n, hipStream_t s);

@@ -434,27 +434,31 @@ __global__ __launch_bounds__(256) void k_reduce(const float* __restrict__ partia
     if (threadIdx.x == 0) *out = (float)(sh[0] * scale);
 }
 
-// Position of voxel (z, p) in the plane-major compact order, or -1 if it is not in S.
-__device__ __forceinline__ int active_pos(const uint64_t* __restrict__ bal, const int* __restrict__ off,
-                                          int64_t nblk, int z, int p) {
-    const int64_t e = (int64_t)z * nblk + (p >> 6);
-    const uint64_t b = bal[e];
-    const int bit = p & 63;
-    if (!((b >> bit) & 1)) return -1;
-    return off[e] + __popcll(b & ((1ull << bit) - 1));
+// ------------------------------------------------------------------------------------
+// Gradient slots. A selected voxel (z, p) whose pixel has r selected planes nearer than z
+// ("rank" r, r < kcap) owns slot (r, p) of a rank-major slice [kcap][H*W] of float4; the
+// gradient kernels write per-view slices [N][kcap][H*W] (or one slice for general warps)
+// and the update kernel sums them.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t plane_bits(int D) { return D == 64 ? ~0ull : ((1ull << D) - 1); }
+
+// rank of plane z in mask word m, or -1 when (z, p) is not selected or beyond kcap
+__device__ __forceinline__ int slot_rank(uint64_t m, int z, int kcap) {
+    if (!((m >> z) & 1)) return -1;
+    const int r = __popcll(m & ((1ull << z) - 1));
+    return r < kcap ? r : -1;
 }
 
 // ------------------------------------------------------------------------------------
-// gradient, general warps: per-ray scans, atomic transposed-bilinear scatter into the
-// compact slots of S
+// gradient, general warps: per-ray scans, atomic transposed-bilinear scatter
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ void scatter_tap(float4* __restrict__ slots, const uint64_t* __restrict__ bal,
-                                            const int* __restrict__ off, int64_t nblk, int z, int p,
-                                            float w, const float4& g) {
+__device__ __forceinline__ void scatter_tap(float4* __restrict__ slots, const uint64_t* __restrict__ mask,
+                                            uint64_t full, int kcap, int HW, int z, int p, float w,
+                                            const float4& g) {
     if (w == 0.0f) return;
-    const int pos = active_pos(bal, off, nblk, z, p);
-    if (pos < 0) return;
-    float* dst = reinterpret_cast<float*>(slots + pos);
+    const int r = slot_rank(mask ? mask[p] : full, z, kcap);
+    if (r < 0) return;
+    float* dst = reinterpret_cast<float*>(slots + (size_t)r * HW + p);
     atomicAdd(dst + 0, w * g.x);
     atomicAdd(dst + 1, w * g.y);
     atomicAdd(dst + 2, w * g.z);
@@ -466,8 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_grad(const void* __restrict__ mpi, i
                                                  const hsgd_warp* __restrict__ warps,
                                                  const float* __restrict__ images,
                                                  const float* __restrict__ dimg,
-                                                 const uint64_t* __restrict__ bal,
-                                                 const int* __restrict__ off, int64_t nblk,
+                                                 const uint64_t* __restrict__ mask, int kcap,
                                                  float inv_n, float4* __restrict__ slots,
                                                  float* __restrict__ partials) {
     __shared__ hsgd_warp sw[MAXD];
@@ -478,6 +481,7 @@ __global__ __launch_bounds__(kBlock) void k_grad(const void* __restrict__ mpi, i
     const int x = blockIdx.x * kTileW + (threadIdx.x & 63);
     const int y = blockIdx.y * kTileH + (threadIdx.x >> 6);
     const int HW = H * W;
+    const uint64_t full = plane_bits(D);
     float sq = 0.0f;
     if (x < W && y < H) {
         float Ts[MAXD];
@@ -529,10 +533,10 @@ __global__ __launch_bounds__(kBlock) void k_grad(const void* __restrict__ mpi, i
                 b0 = s.w * s.x + oa * b0;
                 b1 = s.w * s.y + oa * b1;
                 b2 = s.w * s.z + oa * b2;
-                scatter_tap(slots, bal, off, nblk, z, tp.i00, tp.w00, gs);
-                scatter_tap(slots, bal, off, nblk, z, tp.i10, tp.w10, gs);
-                scatter_tap(slots, bal, off, nblk, z, tp.i01, tp.w01, gs);
-                scatter_tap(slots, bal, off, nblk, z, tp.i11, tp.w11, gs);
+                scatter_tap(slots, mask, full, kcap, HW, z, tp.i00, tp.w00, gs);
+                scatter_tap(slots, mask, full, kcap, HW, z, tp.i10, tp.w10, gs);
+                scatter_tap(slots, mask, full, kcap, HW, z, tp.i01, tp.w01, gs);
+                scatter_tap(slots, mask, full, kcap, HW, z, tp.i11, tp.w11, gs);
             }
         }
     }
@@ -552,10 +556,10 @@ __global__ __launch_bounds__(kBlock) void k_grad(const void* __restrict__ mpi, i
 // (x + ix_z, y + iy_z): with a translation, the four rays whose bilinear footprint covers
 // that cell are the owner and its left, upper and upper-left neighbours, all in the block.
 // Per-ray adjoints are combined across lanes with DPP and across waves through LDS, and
-// each owner writes its cell's gradient once, at the cell's position in S, into the
-// view's slice of the slot buffer. Which cells of a wave's row are in S, and where, comes
-// from the per-block ballot words and offsets (scalar loads); rows without selected cells
-// skip the adjoint.
+// each owner writes its cell's gradient once, into its view's slice of the slots.
+// The front-to-back scan also fetches every owned cell's mask word and keeps one byte per
+// plane (rank + 1, or 0 if the cell is not selected), so the back-to-front scan needs no
+// memory access besides LDS, and skips the adjoint of planes no cell of the rows needs.
 // ------------------------------------------------------------------------------------
 constexpr int kSX = 64, kSY = kShiftOY + 1;
 constexpr int kOX = kShiftOX, kOY = kShiftOY;
@@ -577,58 +581,14 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return x * q + min(x, r) + (b >> 3);
 }
 
-// Per-plane data of one wave, held one plane per lane (lane z = plane z) and fetched with
-// v_readlane inside the plane loops: the shift of the view's warp and which of the wave's
-// owned cells are in S (for its own row of cells and the row below).
-struct PlaneLanes {
-    int ix, iy;
-    float fx, fy;
-    uint32_t w0lo, w0hi, w1lo, w1hi;   // ballot words of the own row's first / second block
-    int o0, o1;                        // their offsets in S
-    int pfirst;                        // first pixel of the own row's first block
-    int flags;                         // bit 0: own row has selected cells; bit 1: row below
-};
-
 __device__ __forceinline__ int rl(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 __device__ __forceinline__ float rlf(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-// Selected cells among the 64 cells X0 .. X0+63 of row Y at plane z (0 <= X < W only).
-__device__ __forceinline__ void row_words(const uint64_t* __restrict__ bal, const int* __restrict__ off,
-                                          int nblk, int z, int Y, int X0, int H, int W, uint64_t& w0,
-                                          uint64_t& w1, int& o0, int& o1, int& pfirst, bool& any) {
-    w0 = w1 = 0;
-    o0 = o1 = 0;
-    pfirst = 0;
-    any = false;
-    const int xa = max(X0, 0), xb = min(X0 + 63, W - 1);
-    if ((unsigned)Y >= (unsigned)H || xa > xb) return;
-    const int pa = Y * W + xa, pb = Y * W + xb;
-    const int b0 = pa >> 6, b1 = pb >> 6;
-    const int e = z * nblk + b0;
-    pfirst = b0 << 6;
-    w0 = bal[e];
-    o0 = off[e];
-    if (b1 != b0) {
-        w1 = bal[e + 1];
-        o1 = off[e + 1];
-    }
-    const int lo = pa & 63;
-    uint64_t m0 = w0 >> lo, m1 = w1;
-    if (b1 == b0) {
-        const int n = pb - pa + 1;
-        m0 &= n >= 64 ? ~0ull : ((1ull << n) - 1);
-    } else {
-        const int hi = pb & 63;
-        m1 &= hi >= 63 ? ~0ull : ((1ull << (hi + 1)) - 1);
-    }
-    any = (m0 | m1) != 0;
-}
-
-// Bilinear sample of plane zbase for the ray of this lane: cx the clamped tap column, r0/r1
-// the (uniform) clamped tap rows, weights with out-of-plane taps already zeroed. All 64
-// lanes must call it together (the right-hand taps come from the next lane).
+// Bilinear sample for the lane's ray from the tap rows r0/r1 (voxel index of the row start,
+// uniform), the clamped tap column and weights with outside taps zeroed. All 64 lanes must
+// call it together (the right-hand taps come from the next lane).
 template <int DT>
 __device__ __forceinline__ float4 shift_sample(const void* __restrict__ mpi, int r0, int r1, unsigned cx,
                                                float w00, float w10, float w01, float w11) {
@@ -642,13 +602,14 @@ __device__ __forceinline__ float4 shift_sample(const void* __restrict__ mpi, int
     return s;
 }
 
-// Sampling of plane z for the lane's ray x at the wave's row y, from the plane's shift.
 struct Tap {
     int r0, r1;
     unsigned cx;
     float w00, w10, w01, w11;
 };
 
+// Taps of plane zbase for the lane's ray x at the wave's row y (uniform); `live` scales the
+// weights (0 for padding planes beyond D).
 __device__ __forceinline__ Tap shift_tap(int zbase, int H, int W, int x, int y, int ix, int iy, float fx,
                                          float fy, float live) {
     Tap t;
@@ -668,13 +629,13 @@ __device__ __forceinline__ Tap shift_tap(int zbase, int H, int W, int x, int y, 
     return t;
 }
 
-template <int DT, int MAXD, bool REGS>
+template <int DT, int MAXD>
 __global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
     const void* __restrict__ mpi, int D, int H, int W, int N, const hsgd_warp* __restrict__ warps,
-    const float* __restrict__ images, const float* __restrict__ dimg, const uint64_t* __restrict__ bal,
-    const int* __restrict__ off, int nblk, int64_t cap, float inv_n, float4* __restrict__ slots,
-    float* __restrict__ partials, int ntx, int nty) {
+    const float* __restrict__ images, const float* __restrict__ dimg, const uint64_t* __restrict__ mask,
+    int kcap, float inv_n, float4* __restrict__ slots, float* __restrict__ partials, int ntx) {
     __shared__ float4 s_h[2][kSX * kSY];
+    __shared__ uint64_t s_bits[kSY];
     __shared__ float sred[kSX * kSY / 64];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int view = tile % N;
@@ -687,60 +648,114 @@ __global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
     const bool ray = lane < kSX - 1 && (unsigned)x < (unsigned)W && (unsigned)y < (unsigned)H;
     const bool owner = lane >= 1 && lane < kSX - 1 && wv >= 1;
     const int HW = H * W;
+    const uint64_t full = plane_bits(D);
 
-    // prologue: lane z < D gathers plane z's shift and this wave's selection words
-    PlaneLanes pl;
-    {
-        pl.ix = pl.iy = 0;
-        pl.fx = pl.fy = 0.0f;
-        uint64_t w0 = 0, w1 = 0;
-        int o0 = 0, o1 = 0, pf = 0, fl = 0;
-        if (lane < D) {
-            const hsgd_warp& w = warps[(size_t)view * D + lane];
-            pl.ix = w.ix;
-            pl.iy = w.iy;
-            pl.fx = w.fx;
-            pl.fy = w.fy;
-            bool any_own, any_below;
-            uint64_t u0, u1;
-            int q0, q1, qf;
-            row_words(bal, off, nblk, lane, y + pl.iy + 1, xl + pl.ix, H, W, u0, u1, q0, q1, qf, any_below);
-            row_words(bal, off, nblk, lane, y + pl.iy, xl + pl.ix, H, W, w0, w1, o0, o1, pf, any_own);
-            fl = (any_own && wv >= 1 ? 1 : 0) | (any_below && wv + 1 < kSY ? 2 : 0);
-        }
-        pl.w0lo = (uint32_t)w0;
-        pl.w0hi = (uint32_t)(w0 >> 32);
-        pl.w1lo = (uint32_t)w1;
-        pl.w1hi = (uint32_t)(w1 >> 32);
-        pl.o0 = o0;
-        pl.o1 = o1;
-        pl.pfirst = pf;
-        pl.flags = fl;
+    // lane z < D holds plane z's shift
+    int lx = 0, ly = 0;
+    float lfx = 0.0f, lfy = 0.0f;
+    if (lane < D) {
+        const hsgd_warp& w = warps[(size_t)view * D + lane];
+        lx = w.ix;
+        ly = w.iy;
+        lfx = w.fx;
+        lfy = w.fy;
     }
 
-    // Plane loops run over MAXD planes without branches (so loads of later planes can be
-    // issued early); planes z >= D sample plane D-1 with zero weight: a transparent plane.
-    float4 smp[REGS ? MAXD : 1];
+    // Both scans run over MAXD planes without branches; planes z >= D sample plane D-1 with
+    // zero weight (a transparent plane) and select nothing. The taps of plane z +- kAhead
+    // are loaded while plane z is processed, and a scheduling fence per plane keeps that
+    // look-ahead (and the register footprint) fixed. The second scan samples the planes
+    // again instead of keeping them in registers: that keeps the kernel small enough for
+    // several workgroups per CU, which hides the per-plane barrier.
+    struct Taps2 {
+        float4 t00, t01;   // taps of rows y0 and y0 + 1 (right-hand taps come from lane + 1)
+    };
+    const void* src = mpi;
+    auto fetch = [&](int z) {
+        Taps2 f;
+        const int ix = rl(lx, z), iy = rl(ly, z);
+        const int zb = min(z, D - 1) * HW;
+        const int Y0 = y + iy;
+        const unsigned cx = (unsigned)min(max(x + ix, 0), W - 1);
+        f.t00 = Vox<DT>::load_row(Vox<DT>::row_ptr(src, zb + min(max(Y0, 0), H - 1) * W), cx);
+        f.t01 = Vox<DT>::load_row(Vox<DT>::row_ptr(src, zb + min(max(Y0 + 1, 0), H - 1) * W), cx);
+        return f;
+    };
+    // the owned cell's mask word (the tap column is the cell's column whenever the cell
+    // lies inside the plane)
+    auto fetch_mask = [&](int z) -> uint64_t {
+        if (!mask) return full;
+        const int ix = rl(lx, z), iy = rl(ly, z);
+        const int Y = min(max(y + iy, 0), H - 1);
+        const unsigned cx = (unsigned)min(max(x + ix, 0), W - 1);
+        return reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(mask) + (size_t)(unsigned)(Y * W) * 8)[cx];
+    };
+    auto sample = [&](int z, const Taps2& f) {
+        const Tap tp = shift_tap(0, H, W, x, y, rl(lx, z), rl(ly, z), rlf(lfx, z), rlf(lfy, z), z < D ? 1.0f : 0.0f);
+        float4 s;
+        s.x = tp.w00 * f.t00.x + tp.w10 * lane_from_next(f.t00.x) + tp.w01 * f.t01.x + tp.w11 * lane_from_next(f.t01.x);
+        s.y = tp.w00 * f.t00.y + tp.w10 * lane_from_next(f.t00.y) + tp.w01 * f.t01.y + tp.w11 * lane_from_next(f.t01.y);
+        s.z = tp.w00 * f.t00.z + tp.w10 * lane_from_next(f.t00.z) + tp.w01 * f.t01.z + tp.w11 * lane_from_next(f.t01.z);
+        s.w = tp.w00 * f.t00.w + tp.w10 * lane_from_next(f.t00.w) + tp.w01 * f.t01.w + tp.w11 * lane_from_next(f.t01.w);
+        return s;
+    };
+    constexpr int kAhead = 2;
+    // Every plane iteration starts with a branch on an opaque, always-true value: the block
+    // boundaries keep the compiler from moving each plane's setup code across planes (which
+    // would keep all of it alive at once).
+    int go = 1;
+
     float Ts[MAXD];
-    float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+    uint32_t code[(MAXD + 3) / 4];               // per plane: rank + 1 of the owned cell, or 0
+    uint64_t own_bits = 0;                       // planes where an owned cell of this wave is selected
 #pragma unroll
-    for (int z = 0; z < MAXD; ++z) {
-        // without REGS (64 planes) the per-plane branch stays: it keeps the scheduler from
-        // hoisting every plane's loads at once
-        if (REGS || z < D) {
-            const float live = z < D ? 1.0f : 0.0f;
-            const Tap tp = shift_tap(min(z, D - 1) * HW, H, W, x, y, rl(pl.ix, z), rl(pl.iy, z), rlf(pl.fx, z),
-                                     rlf(pl.fy, z), live);
-            const float4 s = shift_sample<DT>(mpi, tp.r0, tp.r1, tp.cx, tp.w00, tp.w10, tp.w01, tp.w11);
-            if (REGS) smp[z] = s;
+    for (int i = 0; i < (MAXD + 3) / 4; ++i) code[i] = 0;
+    float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+    {
+        Taps2 q[kAhead];
+        uint64_t qm[kAhead];
+#pragma unroll
+        for (int i = 0; i < kAhead; ++i)
+            if (i < MAXD) {
+                q[i] = fetch(i);
+                qm[i] = fetch_mask(i);
+            }
+#pragma unroll
+        for (int z = 0; z < MAXD; ++z) {
+            asm volatile("" : "+v"(go));
+            if (!__builtin_amdgcn_readfirstlane(go)) break;
+            const Taps2 cur = q[z % kAhead];
+            const uint64_t m = qm[z % kAhead];
+            if (z + kAhead < MAXD) {
+                q[z % kAhead] = fetch(z + kAhead);
+                qm[z % kAhead] = fetch_mask(z + kAhead);
+            }
+            const float4 s = sample(z, cur);
             Ts[z] = T;
             const float wgt = T * s.w;
             c0 += wgt * s.x;
             c1 += wgt * s.y;
             c2 += wgt * s.z;
             T *= 1.0f - s.w;
+            const int Y = y + rl(ly, z), X = x + rl(lx, z);
+            const bool cell = owner && z < D && (unsigned)Y < (unsigned)H && (unsigned)X < (unsigned)W;
+            const int r = cell ? slot_rank(m, z, kcap) : -1;
+            code[z >> 2] |= (uint32_t)(r + 1) << ((z & 3) * 8);
+            if (__ballot(r >= 0)) own_bits |= 1ull << z;
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
+    // planes where the wave below has selected cells: it needs this wave's adjoints
+    if (lane == 0) s_bits[wv] = own_bits;
+    __syncthreads();
+    uint64_t below_bits = 0;
+    if (wv + 1 < kSY) {
+        const uint64_t b = s_bits[wv + 1];
+        below_bits = ((uint64_t)__builtin_amdgcn_readfirstlane((int)(b >> 32)) << 32) |
+                     (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+    }
+    const uint64_t need_bits = own_bits | below_bits;
+
     float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, sq = 0.0f;
     if (ray) {
         const size_t pix = ((size_t)view * H + y) * W + x;
@@ -760,24 +775,27 @@ __global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
         }
     }
     float b0 = 0.0f, b1 = 0.0f, b2 = 0.0f;   // composite behind plane z
-    float4* __restrict__ vslots = slots + (size_t)view * cap;
+    float4* __restrict__ vslots = slots + (size_t)view * kcap * HW;
+    // launder everything the second scan derives its taps from, so that nothing computed
+    // per plane in the first scan is kept alive for it
+    asm volatile("" : "+s"(src), "+v"(lx), "+v"(ly), "+v"(lfx), "+v"(lfy));
+    {
+        Taps2 q[kAhead];
 #pragma unroll
-    for (int zz = 0; zz < MAXD; ++zz) {
-        const int z = MAXD - 1 - zz;
-        if (REGS || z < D) {
-            const int ix = rl(pl.ix, z), iy = rl(pl.iy, z);
-            const float fx = rlf(pl.fx, z), fy = rlf(pl.fy, z);
-            const int flags = rl(pl.flags, z);   // 0 for planes z >= D
-            float4 s;
-            if (REGS) {
-                s = smp[REGS ? z : 0];
-            } else {
-                const Tap tp = shift_tap(min(z, D - 1) * HW, H, W, x, y, ix, iy, fx, fy, z < D ? 1.0f : 0.0f);
-                s = shift_sample<DT>(mpi, tp.r0, tp.r1, tp.cx, tp.w00, tp.w10, tp.w01, tp.w11);
-            }
+        for (int i = 0; i < kAhead; ++i)
+            if (i < MAXD) q[i] = fetch(MAXD - 1 - i);
+#pragma unroll
+        for (int zz = 0; zz < MAXD; ++zz) {
+            const int z = MAXD - 1 - zz;
+            asm volatile("" : "+v"(go));
+            if (!__builtin_amdgcn_readfirstlane(go)) break;
+            const Taps2 cur = q[zz % kAhead];
+            if (zz + kAhead < MAXD) q[zz % kAhead] = fetch(z - kAhead);
+            const float fx = rlf(lfx, z), fy = rlf(lfy, z);
+            const float4 s = sample(z, cur);
             float4* buf = s_h[z & 1];
-            float4 h;
-            if (flags) {
+            float4 h = make_float4(0.f, 0.f, 0.f, 0.f);
+            if ((need_bits >> z) & 1) {
                 const float Tz = Ts[z];
                 const float ca = s.w * Tz;
                 float4 a;
@@ -799,16 +817,9 @@ __global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
             b1 = s.w * s.y + oa * b1;
             b2 = s.w * s.z + oa * b2;
             __syncthreads();
-            if (flags & 1) {
-                const int Y = y + iy;
-                const int X = xl + ix + lane;
-                const int j = Y * W + X - rl(pl.pfirst, z);   // 0..127 inside the row
-                const uint32_t lo = (uint32_t)(j < 64 ? rl(pl.w0lo, z) : rl(pl.w1lo, z));
-                const uint32_t hi = (uint32_t)(j < 64 ? rl(pl.w0hi, z) : rl(pl.w1hi, z));
-                const uint64_t word = ((uint64_t)hi << 32) | lo;
-                const int bit = j & 63;
-                if (owner && (unsigned)X < (unsigned)W && ((word >> bit) & 1)) {
-                    const int pos = (j < 64 ? rl(pl.o0, z) : rl(pl.o1, z)) + __popcll(word & ((1ull << bit) - 1));
+            if ((own_bits >> z) & 1) {
+                const int rc = (int)((code[z >> 2] >> ((z & 3) * 8)) & 0xffu);
+                if (rc) {
                     const float4 hu = buf[threadIdx.x - 64];   // the row above
                     const float gy = 1.0f - fy;
                     float4 c;
@@ -816,9 +827,11 @@ __global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
                     c.y = h.y * gy + hu.y * fy;
                     c.z = h.z * gy + hu.z * fy;
                     c.w = h.w * gy + hu.w * fy;
-                    if (pos < cap) vslots[pos] = c;
+                    const int p = (y + rl(ly, z)) * W + (x + rl(lx, z));
+                    vslots[(size_t)(rc - 1) * HW + p] = c;
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
     if (partials) {
@@ -833,49 +846,72 @@ __global__ __launch_bounds__(256) void k_fill_zero(float4* __restrict__ p, int64
     for (int64_t j = i; j < n; j += stride) p[j] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-// One thread per voxel of S (compact order): sum the view slices, apply the clamped
-// descent step in place and/or write the gradient out. With shift warps, view v holds the
-// voxel only if the voxel lies in v's owner coverage; outside it no ray of v reaches the
-// voxel and the slot is not read.
+// One thread per pixel: for each selected plane (rank r < kcap) sum the view slices, then
+// apply the clamped descent step in place and/or write the gradient out. With shift
+// warps, view v wrote voxel (z, p) only if p lies in v's owner coverage for plane z;
+// outside it no ray of v reaches the voxel and the slot is not read. Workgroup 0 also
+// reduces the loss partials of the gradient kernel (fixed order, FP64).
 template <int DT, bool SHIFT>
 __global__ __launch_bounds__(256) void k_update(void* __restrict__ mpi, int D, int H, int W,
-                                                const int* __restrict__ ids, const int* __restrict__ nact,
-                                                int64_t cap, const float4* __restrict__ slots,
-                                                int nslices, const hsgd_warp* __restrict__ warps,
-                                                int cover_w, int cover_h, float lr_rgb, float lr_a,
-                                                int do_update, float4* __restrict__ grad_out) {
+                                                const uint64_t* __restrict__ mask, int kcap,
+                                                const float4* __restrict__ slots, int nslices,
+                                                const hsgd_warp* __restrict__ warps, int cover_w,
+                                                int cover_h, float lr_rgb, float lr_a, int do_update,
+                                                float4* __restrict__ grad_out,
+                                                const float* __restrict__ partials, int64_t nparts,
+                                                double loss_scale, float* __restrict__ out_loss) {
     extern __shared__ int2 s_off[];   // [nslices][D] (ix, iy) when SHIFT
     if (SHIFT) {
         for (int i = threadIdx.x; i < nslices * D; i += blockDim.x) s_off[i] = make_int2(warps[i].ix, warps[i].iy);
         __syncthreads();
     }
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= *nact || i >= cap) return;
-    const int HW = H * W;
-    const int id = ids[i];
-    const int z = id / HW;
-    const int p = id - z * HW;
-    const int Y = p / W, X = p - Y * W;
-    float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int v = 0; v < nslices; ++v) {
-        if (SHIFT) {
-            const int2 o = s_off[v * D + z];
-            if ((unsigned)(X - o.x) >= (unsigned)cover_w || (unsigned)(Y - o.y) >= (unsigned)cover_h) continue;
+    if (out_loss && blockIdx.x == 0) {
+        __shared__ double sh[256];
+        double acc = 0.0;
+        for (int64_t i = threadIdx.x; i < nparts; i += 256) acc += (double)partials[i];
+        sh[threadIdx.x] = acc;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+            __syncthreads();
         }
-        const float4 t = slots[(size_t)v * cap + i];
-        g.x += t.x;
-        g.y += t.y;
-        g.z += t.z;
-        g.w += t.w;
+        if (threadIdx.x == 0) *out_loss = (float)(sh[0] * loss_scale);
     }
-    if (grad_out) grad_out[id] = g;
-    if (do_update) {
-        float4 v = Vox<DT>::load(mpi, id);
-        v.x = fminf(fmaxf(v.x - lr_rgb * g.x, 0.0f), 1.0f);
-        v.y = fminf(fmaxf(v.y - lr_rgb * g.y, 0.0f), 1.0f);
-        v.z = fminf(fmaxf(v.z - lr_rgb * g.z, 0.0f), 1.0f);
-        v.w = fminf(fmaxf(v.w - lr_a * g.w, 0.0f), 1.0f);
-        Vox<DT>::store(mpi, id, v);
+    const int HW = H * W;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= HW) return;
+    const int Y = p / W, X = p - Y * W;
+    const uint64_t m = (mask ? mask[p] : ~0ull) & plane_bits(D);
+    auto grad_of = [&](int z, int r) {
+        float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int v = 0; v < nslices; ++v) {
+            if (SHIFT) {
+                const int2 o = s_off[v * D + z];
+                if ((unsigned)(X - o.x) >= (unsigned)cover_w || (unsigned)(Y - o.y) >= (unsigned)cover_h) continue;
+            }
+            const float4 t = slots[((size_t)v * kcap + r) * HW + p];
+            g.x += t.x;
+            g.y += t.y;
+            g.z += t.z;
+            g.w += t.w;
+        }
+        return g;
+    };
+    uint64_t b = m;
+    int r = 0;
+    while (b && r < kcap) {
+        const int z = __ffsll((unsigned long long)b) - 1;
+        b &= b - 1;
+        const float4 g = grad_of(z, r++);
+        if (grad_out) grad_out[(size_t)z * HW + p] = g;
+        if (do_update) {
+            float4 v = Vox<DT>::load(mpi, z * HW + p);
+            v.x = fminf(fmaxf(v.x - lr_rgb * g.x, 0.0f), 1.0f);
+            v.y = fminf(fmaxf(v.y - lr_rgb * g.y, 0.0f), 1.0f);
+            v.z = fminf(fmaxf(v.z - lr_rgb * g.z, 0.0f), 1.0f);
+            v.w = fminf(fmaxf(v.w - lr_a * g.w, 0.0f), 1.0f);
+            Vox<DT>::store(mpi, z * HW + p, v);
+        }
     }
 }
 
@@ -983,17 +1019,6 @@ int launch_select(const hsgd_mpi& m, int k, float tau, uint64_t* mask, const Act
     return launch_scan_compact(*as, m.D, HW, plane_off, s);
 }
 
-int launch_active_from_mask(int D, int H, int W, const uint64_t* mask, int kcap, const ActiveSet& as,
-                            hipStream_t s) {
-    const int HW = H * W;
-    {
-        ProfScope ps(HSGD_K_SELECT, s);
-        hipLaunchKernelGGL(k_mask_ballot, dim3((unsigned)ceil_div(HW, 256)), dim3(256), 0, s, mask, D, HW, kcap,
-                           as.bal, as.off, as.nblk);
-    }
-    return launch_scan_compact(as, D, HW, nullptr, s);
-}
-
 int launch_render(const hsgd_mpi& m, const hsgd_views& v, float* out_rgb, float* out_loss,
                   void* ws, hipStream_t s) {
     const RenderWs L = render_ws(m.H, m.W, v.N);
@@ -1011,9 +1036,9 @@ int launch_render(const hsgd_mpi& m, const hsgd_views& v, float* out_rgb, float*
     return (int)hipGetLastError();
 }
 
-int launch_grad_step(const hsgd_mpi& m, const hsgd_views& v, const ActiveSet& as, const float* dimg,
-                     float lr_rgb, float lr_alpha, float* grad_out, float* out_loss, float4* slots,
-                     float* partials, hipStream_t s) {
+int launch_grad_step(const hsgd_mpi& m, const hsgd_views& v, const uint64_t* mask, int kcap,
+                     const float* dimg, float lr_rgb, float lr_alpha, float* grad_out, float* out_loss,
+                     float4* slots, float* partials, hipStream_t s) {
     const int HW = m.H * m.W;
     const float inv_n = 1.0f / (float)v.N;
     const bool shift = (v.flags & HSGD_VIEWS_SHIFT_ONLY) != 0;
@@ -1032,50 +1057,39 @@ int launch_grad_step(const hsgd_mpi& m, const hsgd_views& v, const ActiveSet& as
         nparts = (int64_t)ntx * nty * v.N;
         const dim3 grid((unsigned)nparts);
         ProfScope ps(HSGD_K_GRAD, s);
-#define HSGD_SHIFT_LAUNCH(MD, REGS)                                                                         \
-    hipLaunchKernelGGL((k_grad_shift<DT, MD, REGS>), grid, dim3(kSX * kSY), 0, s, m.rgba, m.D, m.H, m.W, v.N, \
-                       v.warps, v.images, dimg, as.bal, as.off, as.nblk, as.cap, inv_n, slots,               \
-                       out_loss ? partials : nullptr, ntx, nty)
-        HSGD_DISPATCH_T(m.dtype, switch (maxd_class(m.D)) {
-            case 8: HSGD_SHIFT_LAUNCH(8, true); break;
-            case 16: HSGD_SHIFT_LAUNCH(16, true); break;
-            case 32: HSGD_SHIFT_LAUNCH(32, true); break;
-            default: HSGD_SHIFT_LAUNCH(64, false); break;
-        });
-#undef HSGD_SHIFT_LAUNCH
+        HSGD_DISPATCH_T(m.dtype, HSGD_DISPATCH_D(m.D, hipLaunchKernelGGL((k_grad_shift<DT, MD>), grid, dim3(kSX * kSY),
+                                                                        0, s, m.rgba, m.D, m.H, m.W, v.N, v.warps,
+                                                                        v.images, dimg, mask, kcap, inv_n, slots,
+                                                                        out_loss ? partials : nullptr, ntx)));
     } else {
         {
             ProfScope ps(HSGD_K_FILL, s);
-            hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)std::min<int64_t>(ceil_div(as.cap, 256), 8192)), dim3(256),
-                               0, s, slots, as.cap);
+            const int64_t n = (int64_t)kcap * HW;
+            hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)std::min<int64_t>(ceil_div(n, 256), 8192)), dim3(256), 0, s,
+                               slots, n);
         }
         const dim3 grid((unsigned)ceil_div(m.W, kTileW), (unsigned)ceil_div(m.H, kTileH), (unsigned)v.N);
         nparts = (int64_t)grid.x * grid.y * grid.z;
         ProfScope ps(HSGD_K_GRAD, s);
         HSGD_DISPATCH_T(m.dtype, HSGD_DISPATCH_D(m.D, hipLaunchKernelGGL((k_grad<DT, MD>), grid, dim3(kBlock), 0, s,
                                                                         m.rgba, m.D, m.H, m.W, v.warps, v.images, dimg,
-                                                                        as.bal, as.off, as.nblk, inv_n, slots,
+                                                                        mask, kcap, inv_n, slots,
                                                                         out_loss ? partials : nullptr)));
     }
     const int do_update = (lr_rgb != 0.0f || lr_alpha != 0.0f) ? 1 : 0;
-    if (do_update || grad_out) {
+    if (do_update || grad_out || out_loss) {
         ProfScope ps(HSGD_K_UPDATE, s);
-        const dim3 grid((unsigned)ceil_div(as.cap, 256));
-        if (shift) {
-            const size_t lds = sizeof(int2) * (size_t)v.N * m.D;
-            HSGD_DISPATCH_T(m.dtype, hipLaunchKernelGGL((k_update<DT, true>), grid, dim3(256), lds, s, m.rgba, m.D, m.H,
-                                                        m.W, as.ids, as.nact, as.cap, slots, v.N, v.warps, cover_w,
-                                                        cover_h, lr_rgb, lr_alpha, do_update,
-                                                        reinterpret_cast<float4*>(grad_out)));
+        const dim3 grid((unsigned)ceil_div(HW, 256));
+        const size_t lds = shift ? sizeof(int2) * (size_t)v.N * m.D : 0;
+        HSGD_DISPATCH_T(m.dtype, if (shift) {
+            hipLaunchKernelGGL((k_update<DT, true>), grid, dim3(256), lds, s, m.rgba, m.D, m.H, m.W, mask, kcap,
+                               slots, v.N, v.warps, cover_w, cover_h, lr_rgb, lr_alpha, do_update,
+                               reinterpret_cast<float4*>(grad_out), partials, nparts, 0.5 / v.N, out_loss);
         } else {
-            HSGD_DISPATCH_T(m.dtype, hipLaunchKernelGGL((k_update<DT, false>), grid, dim3(256), 0, s, m.rgba, m.D, m.H,
-                                                        m.W, as.ids, as.nact, as.cap, slots, 1, v.warps, 0, 0, lr_rgb,
-                                                        lr_alpha, do_update, reinterpret_cast<float4*>(grad_out)));
-        }
-    }
-    if (out_loss) {
-        ProfScope ps(HSGD_K_REDUCE, s);
-        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, nparts, 0.5 / v.N, out_loss);
+            hipLaunchKernelGGL((k_update<DT, false>), grid, dim3(256), 0, s, m.rgba, m.D, m.H, m.W, mask, kcap,
+                               slots, 1, v.warps, 0, 0, lr_rgb, lr_alpha, do_update,
+                               reinterpret_cast<float4*>(grad_out), partials, nparts, 0.5 / v.N, out_loss);
+        });
     }
     return (int)hipGetLastError();
 }
