@@ -68,6 +68,8 @@ hsgd_status hsgd_grad_step(hsgd_mpi* m, const hsgd_views* v, const uint64_t* mas
     if (st) return st;
     if (!mask) kcap = m->D;
     if (kcap < 1 || kcap > m->D) return fail(HSGD_E_ARG, "%s: kcap=%d outside [1, D=%d]", fn, kcap, m->D);
+    if ((int64_t)kcap * m->H * m->W >= ((int64_t)1 << 28))
+        return fail(HSGD_E_SHAPE, "%s: kcap*H*W must stay below 2^28 gradient slots per view", fn);
     if (!std::isfinite(lr_rgb) || !std::isfinite(lr_alpha))
         return fail(HSGD_E_ARG, "%s: learning rates must be finite", fn);
     const GradWs L = grad_ws(m->D, m->H, m->W, v->N, kcap);
@@ -141,6 +143,8 @@ hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
     }
     const hsgd_mpi& top = levels[L - 1];
     if (sel.k < 1 || sel.k > top.D) return fail(HSGD_E_ARG, "%s: k=%d outside [1, D]", fn, sel.k);
+    if ((int64_t)sel.k * top.H * top.W >= ((int64_t)1 << 28))
+        return fail(HSGD_E_SHAPE, "%s: k*H*W must stay below 2^28 gradient slots per view", fn);
     if (std::isnan(sel.tau)) return fail(HSGD_E_ARG, "%s: tau is NaN", fn);
     if (!std::isfinite(lr_rgb) || !std::isfinite(lr_alpha))
         return fail(HSGD_E_ARG, "%s: learning rates must be finite", fn);

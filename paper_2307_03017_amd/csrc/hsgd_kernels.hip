@@ -586,50 +586,7 @@ __device__ __forceinline__ float rlf(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-// Bilinear sample for the lane's ray from the tap rows r0/r1 (voxel index of the row start,
-// uniform), the clamped tap column and weights with outside taps zeroed. All 64 lanes must
-// call it together (the right-hand taps come from the next lane).
-template <int DT>
-__device__ __forceinline__ float4 shift_sample(const void* __restrict__ mpi, int r0, int r1, unsigned cx,
-                                               float w00, float w10, float w01, float w11) {
-    const float4 t00 = Vox<DT>::load_row(Vox<DT>::row_ptr(mpi, r0), cx);
-    const float4 t01 = Vox<DT>::load_row(Vox<DT>::row_ptr(mpi, r1), cx);
-    float4 s;
-    s.x = w00 * t00.x + w10 * lane_from_next(t00.x) + w01 * t01.x + w11 * lane_from_next(t01.x);
-    s.y = w00 * t00.y + w10 * lane_from_next(t00.y) + w01 * t01.y + w11 * lane_from_next(t01.y);
-    s.z = w00 * t00.z + w10 * lane_from_next(t00.z) + w01 * t01.z + w11 * lane_from_next(t01.z);
-    s.w = w00 * t00.w + w10 * lane_from_next(t00.w) + w01 * t01.w + w11 * lane_from_next(t01.w);
-    return s;
-}
-
-struct Tap {
-    int r0, r1;
-    unsigned cx;
-    float w00, w10, w01, w11;
-};
-
-// Taps of plane zbase for the lane's ray x at the wave's row y (uniform); `live` scales the
-// weights (0 for padding planes beyond D).
-__device__ __forceinline__ Tap shift_tap(int zbase, int H, int W, int x, int y, int ix, int iy, float fx,
-                                         float fy, float live) {
-    Tap t;
-    const int Y0 = y + iy;
-    const bool y0ok = (unsigned)Y0 < (unsigned)H, y1ok = (unsigned)(Y0 + 1) < (unsigned)H;
-    t.r0 = zbase + min(max(Y0, 0), H - 1) * W;
-    t.r1 = zbase + min(max(Y0 + 1, 0), H - 1) * W;
-    const int X0 = x + ix;
-    t.cx = (unsigned)min(max(X0, 0), W - 1);
-    const bool x0ok = (unsigned)X0 < (unsigned)W, x1ok = (unsigned)(X0 + 1) < (unsigned)W;
-    const float gy = y0ok ? (1.0f - fy) * live : 0.0f, hy = y1ok ? fy * live : 0.0f;   // uniform
-    const float gx = 1.0f - fx;
-    t.w00 = x0ok ? gx * gy : 0.0f;
-    t.w10 = x1ok ? fx * gy : 0.0f;
-    t.w01 = x0ok ? gx * hy : 0.0f;
-    t.w11 = x1ok ? fx * hy : 0.0f;
-    return t;
-}
-
-template <int DT, int MAXD>
+template <int DT, int MAXD, bool MASKED>
 __global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
     const void* __restrict__ mpi, int D, int H, int W, int N, const hsgd_warp* __restrict__ warps,
     const float* __restrict__ images, const float* __restrict__ dimg, const uint64_t* __restrict__ mask,
@@ -650,53 +607,68 @@ __global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
     const int HW = H * W;
     const uint64_t full = plane_bits(D);
 
-    // lane z < D holds plane z's shift
+    // lane z < D holds plane z's shift and its four bilinear weights for this wave's row
+    // (taps in rows outside the plane already zeroed); lanes z >= D hold zeros
     int lx = 0, ly = 0;
-    float lfx = 0.0f, lfy = 0.0f;
+    float lw00 = 0.0f, lw10 = 0.0f, lw01 = 0.0f, lw11 = 0.0f, lfx = 0.0f, lfy = 0.0f;
     if (lane < D) {
         const hsgd_warp& w = warps[(size_t)view * D + lane];
         lx = w.ix;
         ly = w.iy;
         lfx = w.fx;
         lfy = w.fy;
+        const int Y0 = y + ly;
+        const float gy = (unsigned)Y0 < (unsigned)H ? 1.0f - lfy : 0.0f;
+        const float hy = (unsigned)(Y0 + 1) < (unsigned)H ? lfy : 0.0f;
+        lw00 = (1.0f - lfx) * gy;
+        lw10 = lfx * gy;
+        lw01 = (1.0f - lfx) * hy;
+        lw11 = lfx * hy;
     }
 
-    // Both scans run over MAXD planes without branches; planes z >= D sample plane D-1 with
-    // zero weight (a transparent plane) and select nothing. The taps of plane z +- kAhead
-    // are loaded while plane z is processed, and a scheduling fence per plane keeps that
-    // look-ahead (and the register footprint) fixed. The second scan samples the planes
-    // again instead of keeping them in registers: that keeps the kernel small enough for
-    // several workgroups per CU, which hides the per-plane barrier.
+    // Both scans run over MAXD planes; planes z >= D sample plane D-1 with zero weights (a
+    // transparent plane) and select nothing. The taps of plane z +- kAhead are loaded while
+    // plane z is processed, and a scheduling fence per plane keeps that look-ahead (and the
+    // register footprint) fixed. The second scan samples the planes again instead of
+    // keeping them in registers: that keeps the kernel small enough for several workgroups
+    // per CU, which hides the per-plane barrier.
     struct Taps2 {
         float4 t00, t01;   // taps of rows y0 and y0 + 1 (right-hand taps come from lane + 1)
     };
-    const void* src = mpi;
-    auto fetch = [&](int z) {
+    // zstride: the plane stride HW, passed laundered to the second scan so that the
+    // compiler cannot prove its loads equal the first scan's and keep those alive instead
+    auto fetch = [&](int z, int zstride) {
         Taps2 f;
         const int ix = rl(lx, z), iy = rl(ly, z);
-        const int zb = min(z, D - 1) * HW;
+        const int zb = min(z, D - 1) * zstride;
         const int Y0 = y + iy;
         const unsigned cx = (unsigned)min(max(x + ix, 0), W - 1);
-        f.t00 = Vox<DT>::load_row(Vox<DT>::row_ptr(src, zb + min(max(Y0, 0), H - 1) * W), cx);
-        f.t01 = Vox<DT>::load_row(Vox<DT>::row_ptr(src, zb + min(max(Y0 + 1, 0), H - 1) * W), cx);
+        f.t00 = Vox<DT>::load_row(Vox<DT>::row_ptr(mpi, zb + min(max(Y0, 0), H - 1) * W), cx);
+        f.t01 = Vox<DT>::load_row(Vox<DT>::row_ptr(mpi, zb + min(max(Y0 + 1, 0), H - 1) * W), cx);
         return f;
     };
     // the owned cell's mask word (the tap column is the cell's column whenever the cell
     // lies inside the plane)
     auto fetch_mask = [&](int z) -> uint64_t {
-        if (!mask) return full;
+        if (!MASKED) return full;
         const int ix = rl(lx, z), iy = rl(ly, z);
         const int Y = min(max(y + iy, 0), H - 1);
         const unsigned cx = (unsigned)min(max(x + ix, 0), W - 1);
-        return reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(mask) + (size_t)(unsigned)(Y * W) * 8)[cx];
+        const char* row = reinterpret_cast<const char*>(mask) + (size_t)(unsigned)(Y * W) * 8;
+        return *reinterpret_cast<const uint64_t*>(row + (cx << 3));
     };
     auto sample = [&](int z, const Taps2& f) {
-        const Tap tp = shift_tap(0, H, W, x, y, rl(lx, z), rl(ly, z), rlf(lfx, z), rlf(lfy, z), z < D ? 1.0f : 0.0f);
+        const int X0 = x + rl(lx, z);
+        const float u00 = rlf(lw00, z), u10 = rlf(lw10, z), u01 = rlf(lw01, z), u11 = rlf(lw11, z);
+        const bool x0ok = (unsigned)X0 < (unsigned)W, x1ok = (unsigned)(X0 + 1) < (unsigned)W;
+        const float w00 = x0ok ? u00 : 0.0f, w01 = x0ok ? u01 : 0.0f;
+        const float w10 = x1ok ? u10 : 0.0f, w11 = x1ok ? u11 : 0.0f;
+        // the next lane's taps enter as the first FMA operand, so DPP folds into the FMA
         float4 s;
-        s.x = tp.w00 * f.t00.x + tp.w10 * lane_from_next(f.t00.x) + tp.w01 * f.t01.x + tp.w11 * lane_from_next(f.t01.x);
-        s.y = tp.w00 * f.t00.y + tp.w10 * lane_from_next(f.t00.y) + tp.w01 * f.t01.y + tp.w11 * lane_from_next(f.t01.y);
-        s.z = tp.w00 * f.t00.z + tp.w10 * lane_from_next(f.t00.z) + tp.w01 * f.t01.z + tp.w11 * lane_from_next(f.t01.z);
-        s.w = tp.w00 * f.t00.w + tp.w10 * lane_from_next(f.t00.w) + tp.w01 * f.t01.w + tp.w11 * lane_from_next(f.t01.w);
+        s.x = __builtin_fmaf(lane_from_next(f.t01.x), w11, __builtin_fmaf(lane_from_next(f.t00.x), w10, __builtin_fmaf(f.t01.x, w01, f.t00.x * w00)));
+        s.y = __builtin_fmaf(lane_from_next(f.t01.y), w11, __builtin_fmaf(lane_from_next(f.t00.y), w10, __builtin_fmaf(f.t01.y, w01, f.t00.y * w00)));
+        s.z = __builtin_fmaf(lane_from_next(f.t01.z), w11, __builtin_fmaf(lane_from_next(f.t00.z), w10, __builtin_fmaf(f.t01.z, w01, f.t00.z * w00)));
+        s.w = __builtin_fmaf(lane_from_next(f.t01.w), w11, __builtin_fmaf(lane_from_next(f.t00.w), w10, __builtin_fmaf(f.t01.w, w01, f.t00.w * w00)));
         return s;
     };
     constexpr int kAhead = 2;
@@ -717,7 +689,7 @@ __global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
 #pragma unroll
         for (int i = 0; i < kAhead; ++i)
             if (i < MAXD) {
-                q[i] = fetch(i);
+                q[i] = fetch(i, HW);
                 qm[i] = fetch_mask(i);
             }
 #pragma unroll
@@ -727,7 +699,7 @@ __global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
             const Taps2 cur = q[z % kAhead];
             const uint64_t m = qm[z % kAhead];
             if (z + kAhead < MAXD) {
-                q[z % kAhead] = fetch(z + kAhead);
+                q[z % kAhead] = fetch(z + kAhead, HW);
                 qm[z % kAhead] = fetch_mask(z + kAhead);
             }
             const float4 s = sample(z, cur);
@@ -739,9 +711,12 @@ __global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
             T *= 1.0f - s.w;
             const int Y = y + rl(ly, z), X = x + rl(lx, z);
             const bool cell = owner && z < D && (unsigned)Y < (unsigned)H && (unsigned)X < (unsigned)W;
-            const int r = cell ? slot_rank(m, z, kcap) : -1;
-            code[z >> 2] |= (uint32_t)(r + 1) << ((z & 3) * 8);
-            if (__ballot(r >= 0)) own_bits |= 1ull << z;
+            // branch-free: rank + 1 of the owned cell's plane z if selected, else 0
+            const uint32_t sel = cell ? (uint32_t)((m >> z) & 1) : 0u;
+            const uint32_t rank = (uint32_t)__popcll(m & ((1ull << z) - 1));
+            const uint32_t rc = (sel && rank < (uint32_t)kcap) ? rank + 1 : 0u;
+            code[z >> 2] |= rc << ((z & 3) * 8);
+            if (__ballot(rc != 0)) own_bits |= 1ull << z;
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -776,21 +751,22 @@ __global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
     }
     float b0 = 0.0f, b1 = 0.0f, b2 = 0.0f;   // composite behind plane z
     float4* __restrict__ vslots = slots + (size_t)view * kcap * HW;
-    // launder everything the second scan derives its taps from, so that nothing computed
-    // per plane in the first scan is kept alive for it
-    asm volatile("" : "+s"(src), "+v"(lx), "+v"(ly), "+v"(lfx), "+v"(lfy));
+    // launder what the second scan derives its taps from, so that nothing computed per
+    // plane in the first scan is kept alive for it
+    int HW2 = HW;
+    asm volatile("" : "+s"(HW2), "+v"(lx), "+v"(ly), "+v"(lw00), "+v"(lw10), "+v"(lw01), "+v"(lw11));
     {
         Taps2 q[kAhead];
 #pragma unroll
         for (int i = 0; i < kAhead; ++i)
-            if (i < MAXD) q[i] = fetch(MAXD - 1 - i);
+            if (i < MAXD) q[i] = fetch(MAXD - 1 - i, HW2);
 #pragma unroll
         for (int zz = 0; zz < MAXD; ++zz) {
             const int z = MAXD - 1 - zz;
             asm volatile("" : "+v"(go));
             if (!__builtin_amdgcn_readfirstlane(go)) break;
             const Taps2 cur = q[zz % kAhead];
-            if (zz + kAhead < MAXD) q[zz % kAhead] = fetch(z - kAhead);
+            if (zz + kAhead < MAXD) q[zz % kAhead] = fetch(z - kAhead, HW2);
             const float fx = rlf(lfx, z), fy = rlf(lfy, z);
             const float4 s = sample(z, cur);
             float4* buf = s_h[z & 1];
@@ -827,8 +803,8 @@ __global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
                     c.y = h.y * gy + hu.y * fy;
                     c.z = h.z * gy + hu.z * fy;
                     c.w = h.w * gy + hu.w * fy;
-                    const int p = (y + rl(ly, z)) * W + (x + rl(lx, z));
-                    vslots[(size_t)(rc - 1) * HW + p] = c;
+                    const unsigned idx = (unsigned)((rc - 1) * HW + (y + rl(ly, z)) * W + (x + rl(lx, z)));
+                    *reinterpret_cast<float4*>(reinterpret_cast<char*>(vslots) + (idx << 4)) = c;
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -1057,10 +1033,19 @@ int launch_grad_step(const hsgd_mpi& m, const hsgd_views& v, const uint64_t* mas
         nparts = (int64_t)ntx * nty * v.N;
         const dim3 grid((unsigned)nparts);
         ProfScope ps(HSGD_K_GRAD, s);
-        HSGD_DISPATCH_T(m.dtype, HSGD_DISPATCH_D(m.D, hipLaunchKernelGGL((k_grad_shift<DT, MD>), grid, dim3(kSX * kSY),
-                                                                        0, s, m.rgba, m.D, m.H, m.W, v.N, v.warps,
-                                                                        v.images, dimg, mask, kcap, inv_n, slots,
-                                                                        out_loss ? partials : nullptr, ntx)));
+        if (mask) {
+            HSGD_DISPATCH_T(m.dtype, HSGD_DISPATCH_D(m.D, hipLaunchKernelGGL((k_grad_shift<DT, MD, true>), grid,
+                                                                            dim3(kSX * kSY), 0, s, m.rgba, m.D, m.H, m.W,
+                                                                            v.N, v.warps, v.images, dimg, mask, kcap,
+                                                                            inv_n, slots, out_loss ? partials : nullptr,
+                                                                            ntx)));
+        } else {
+            HSGD_DISPATCH_T(m.dtype, HSGD_DISPATCH_D(m.D, hipLaunchKernelGGL((k_grad_shift<DT, MD, false>), grid,
+                                                                            dim3(kSX * kSY), 0, s, m.rgba, m.D, m.H, m.W,
+                                                                            v.N, v.warps, v.images, dimg, mask, kcap,
+                                                                            inv_n, slots, out_loss ? partials : nullptr,
+                                                                            ntx)));
+        }
     } else {
         {
             ProfScope ps(HSGD_K_FILL, s);
