@@ -1,0 +1,160 @@
+"""Summaries of rocprofv3 output for the library's kernels.
+
+    # kernel durations (rocprofv3 --kernel-trace --stats --output-format csv)
+    python -m paper_2307_03017_amd.profiling stats <kernel_stats.csv> --cmd "<rocprofv3 command>" --md out.md
+
+    # HBM traffic per launch from two counter runs (FETCH_SIZE, then WRITE_SIZE), scaled by
+    # what the same counters read for the library's plain FP32 copy kernel (k_convert) over a
+    # buffer of known size
+    python -m paper_2307_03017_amd.profiling traffic --fetch <fetch counter_collection.csv> \\
+        --write <write counter_collection.csv> --kernel k_grad_shift --copy-bytes 268435456 \\
+        --cmd "<commands>" --json out.json --md out.md
+"""
+
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import re
+from collections import defaultdict
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(_PKG, "csrc", "hsgd_kernels.hip"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(name: str) -> str:
+    """'void hsgd::(anonymous namespace)::k_grad_shift<0, 32, true>(...)' -> 'k_grad_shift<0, 32, true>'"""
+    name = name.split("(void")[0] if name.startswith("void ") else name
+    name = re.sub(r"^void\s+", "", name)
+    name = name.replace("hsgd::(anonymous namespace)::", "")
+    depth = 0
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return name[:i]
+    return name
+
+
+def read_stats(path: str):
+    rows = []
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            keys = {k.lower(): k for k in r}
+            name = r[keys.get("name", "Name")]
+            calls = int(float(r[keys["calls"]]))
+            tot = float(r[keys.get("totaldurationns", keys.get("duration (nsec)", "TotalDurationNs"))])
+            avg = float(r[keys.get("averagens", keys.get("average (nsec)", "AverageNs"))])
+            mn = float(r[keys.get("minns", keys.get("min (nsec)", "MinNs"))])
+            mx = float(r[keys.get("maxns", keys.get("max (nsec)", "MaxNs"))])
+            rows.append(dict(name=short_name(name), calls=calls, total_us=tot / 1e3, avg_us=avg / 1e3,
+                             min_us=mn / 1e3, max_us=mx / 1e3))
+    return rows
+
+
+def stats_md(rows, cmd: str) -> str:
+    total = sum(r["total_us"] for r in rows) or 1.0
+    out = ["# Kernel durations", "", "Command:", "", "```", cmd, "```", "",
+           "| kernel | calls | avg us | min us | max us | share |", "|---|---:|---:|---:|---:|---:|"]
+    for r in sorted(rows, key=lambda r: -r["total_us"]):
+        out.append(f"| `{r['name']}` | {r['calls']} | {r['avg_us']:.1f} | {r['min_us']:.1f} | "
+                   f"{r['max_us']:.1f} | {100 * r['total_us'] / total:.1f}% |")
+    return "\n".join(out) + "\n"
+
+
+def _counter_rows(path: str, counter: str):
+    """Per dispatch: (kernel short name, grid size, counter value)."""
+    per = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] != counter:
+                continue
+            key = (r["Dispatch_Id"], short_name(r["Kernel_Name"]), int(r["Grid_Size"]))
+            per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    return [(k[1], k[2], v) for k, v in per.items()]
+
+
+def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, copy_kernel: str = "k_convert<0, 0>"):
+    f = _counter_rows(fetch_csv, "FETCH_SIZE")
+    w = _counter_rows(write_csv, "WRITE_SIZE")
+    cf = [v for n, g, v in f if n == copy_kernel]
+    cw = [v for n, g, v in w if n == copy_kernel]
+    if not cf or not cw:
+        raise SystemExit("no copy-kernel dispatches in the counter files")
+    # the copy reads and writes copy_bytes/2 each (copy_bytes counts both directions)
+    f_factor = (copy_bytes / 2) / (1024.0 * sum(cf) / len(cf))
+    w_factor = (copy_bytes / 2) / (1024.0 * sum(cw) / len(cw))
+    fk = defaultdict(list)
+    wk = defaultdict(list)
+    for n, g, v in f:
+        if n.startswith(kernel):
+            fk[(n, g)].append(v * 1024.0 * f_factor)
+    for n, g, v in w:
+        if n.startswith(kernel):
+            wk[(n, g)].append(v * 1024.0 * w_factor)
+    launches = []
+    for key in sorted(fk):
+        rb = sum(fk[key]) / len(fk[key])
+        wb = sum(wk.get(key, [0.0])) / max(len(wk.get(key, [])), 1)
+        launches.append(dict(kernel=key[0], grid=key[1], read_bytes=rb, write_bytes=wb))
+    mean = sum(l["read_bytes"] + l["write_bytes"] for l in launches) / max(len(launches), 1)
+    return dict(kernel=kernel, fetch_factor=f_factor, write_factor=w_factor, launches=launches,
+                hbm_bytes_per_launch=mean, kernel_source_hash=kernel_source_hash())
+
+
+def traffic_md(t, cmd: str) -> str:
+    out = ["# HBM traffic per launch", "", "Commands:", "", "```", cmd, "```", "",
+           f"Calibration with the library's plain FP32 copy kernel over a buffer of known size: "
+           f"FETCH_SIZE x {t['fetch_factor']:.3f}, WRITE_SIZE x {t['write_factor']:.3f}.", "",
+           f"Kernel source hash: `{t['kernel_source_hash']}`", "",
+           "| kernel | grid | read MB | write MB |", "|---|---:|---:|---:|"]
+    for l in t["launches"]:
+        out.append(f"| `{l['kernel']}` | {l['grid']} | {l['read_bytes'] / 1e6:.1f} | {l['write_bytes'] / 1e6:.1f} |")
+    out += ["", f"Mean over these launch sizes: {t['hbm_bytes_per_launch'] / 1e6:.1f} MB per launch."]
+    return "\n".join(out) + "\n"
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd_name", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("csv")
+    a.add_argument("--cmd", default="")
+    a.add_argument("--md")
+    b = sub.add_parser("traffic")
+    b.add_argument("--fetch", required=True)
+    b.add_argument("--write", required=True)
+    b.add_argument("--kernel", required=True)
+    b.add_argument("--copy-bytes", type=int, required=True)
+    b.add_argument("--cmd", default="")
+    b.add_argument("--json")
+    b.add_argument("--md")
+    args = ap.parse_args(argv)
+    if args.cmd_name == "stats":
+        md = stats_md(read_stats(args.csv), args.cmd)
+        if args.md:
+            open(args.md, "w").write(md)
+        print(md)
+    else:
+        t = traffic(args.fetch, args.write, args.kernel, args.copy_bytes)
+        if args.json:
+            json.dump(t, open(args.json, "w"), indent=1)
+        md = traffic_md(t, args.cmd)
+        if args.md:
+            open(args.md, "w").write(md)
+        print(md)
+
+
+if __name__ == "__main__":
+    main()
