@@ -1,50 +1,79 @@
-"""Central finite differences of the FP64 oracle's photometric loss for single MPI scalars at
-full frame size, evaluated on crops.
+"""Exact evaluations of the FP64 oracle's photometric loss for one MPI scalar at full frame
+size, on per-plane crops.
 
 With translation warps a voxel (z, Y, X) is read only by the rays of a 2x2 pixel patch per
 view, so the loss difference between M + h e and M - h e is confined to those pixels. Each
-view's patch is rendered by the oracle from an MPI crop that holds every tap of the patch's
-rays (all planes); a translation map renders a crop exactly like the full frame. Taps outside
-the real frame fall outside the crop as well, so zero padding agrees.
+view's patch (with a one-pixel margin) is rendered by the oracle from a small MPI whose plane
+z' is the patch's tap window on plane z' of the full MPI (zero outside the frame, matching
+zero padding); every plane gets its own translation so that the crop renders exactly like
+the full frame. A crop render is therefore only patch-sized, whatever the shifts.
 """
 
 import numpy as np
 
+MARGIN = 2          # view pixels around the 2x2 patch
+PAD = 2             # MPI pixels around each plane's tap window
 
-def _patch_loss(O, Mc, G_i, tgt, r0, c0, rows, cols, N):
-    C = O.render_view(Mc, G_i)[0]
-    d = C[rows[0] - r0:rows[1] - r0 + 1, cols[0] - c0:cols[1] - c0 + 1] - tgt
+
+def _crop_problem(M, Gi, rows, cols):
+    D, H, W, _ = M.shape
+    h = rows[1] - rows[0] + 1
+    w = cols[1] - cols[0] + 1
+    ch_, cw_ = h + 2 * PAD, w + 2 * PAD
+    Mc = np.zeros((D, ch_, cw_, 4))
+    Gc = np.zeros((D, 3, 3))
+    origins = []
+    for z in range(D):
+        sx, sy = Gi[z, 0, 2], Gi[z, 1, 2]
+        ox = cols[0] + int(np.floor(sx)) - PAD
+        oy = rows[0] + int(np.floor(sy)) - PAD
+        ys, xs = slice(max(oy, 0), min(oy + ch_, H)), slice(max(ox, 0), min(ox + cw_, W))
+        if ys.start < ys.stop and xs.start < xs.stop:
+            Mc[z, ys.start - oy:ys.stop - oy, xs.start - ox:xs.stop - ox] = M[z, ys, xs]
+        # crop-view pixel (a, b) = view pixel (cols[0] + a, rows[0] + b); its tap in the
+        # plane crop sits at (cols[0] + a + sx - ox, ...)
+        Gc[z] = np.eye(3)
+        Gc[z, 0, 2] = (cols[0] - ox) + sx
+        Gc[z, 1, 2] = (rows[0] - oy) + sy
+        origins.append((oy, ox))
+    return Mc, Gc, origins
+
+
+def _patch_loss(O, Mc, Gc, tgt, h, w, N):
+    C = O.render_view(Mc, Gc)[0][:h, :w]
+    d = C - tgt
     return float(np.sum(d * d) / (2.0 * N))
 
 
 def fd_scalar(O, M, G, targets, idx, h=1e-3):
-    """Central difference of the oracle loss w.r.t. M[idx] (idx = (z, Y, X, ch))."""
+    """Central difference of the oracle loss w.r.t. M[idx] (idx = (z, Y, X, ch)); G holds
+    the oracle's view-to-reference maps, which must be pure translations."""
     D, H, W, _ = M.shape
     N = len(G)
     z, Y, X, ch = idx
     total = 0.0
     for i in range(N):
-        sx = G[i, :, 0, 2]
-        sy = G[i, :, 1, 2]
-        fx, fy = int(np.floor(sx[z])), int(np.floor(sy[z]))
-        # view pixels whose taps at plane z can include (X, Y), with one pixel of margin
-        rows = (max(Y - fy - 2, 0), min(Y - fy + 1, H - 1))
-        cols = (max(X - fx - 2, 0), min(X - fx + 1, W - 1))
+        fx, fy = int(np.floor(G[i, z, 0, 2])), int(np.floor(G[i, z, 1, 2]))
+        rows = (max(Y - fy - MARGIN, 0), min(Y - fy + MARGIN - 1, H - 1))
+        cols = (max(X - fx - MARGIN, 0), min(X - fx + MARGIN - 1, W - 1))
         if rows[0] > rows[1] or cols[0] > cols[1]:
             continue
-        # MPI crop holding every tap of those rays on every plane (the crop is also the
-        # rendered view window, with the same origin)
-        r0 = max(rows[0] + int(np.floor(sy.min())) - 1, 0)
-        r1 = min(rows[1] + int(np.floor(sy.max())) + 2, H - 1)
-        c0 = max(cols[0] + int(np.floor(sx.min())) - 1, 0)
-        c1 = min(cols[1] + int(np.floor(sx.max())) + 2, W - 1)
-        r0, c0 = min(r0, rows[0]), min(c0, cols[0])
-        r1, c1 = max(r1, rows[1]), max(c1, cols[1])
-        Mc = M[:, r0:r1 + 1, c0:c1 + 1].copy()
+        hh, ww = rows[1] - rows[0] + 1, cols[1] - cols[0] + 1
+        Mc, Gc, origins = _crop_problem(M, G[i], rows, cols)
+        oy, ox = origins[z]
+        cy, cx = Y - oy, X - ox
+        if not (0 <= cy < Mc.shape[1] and 0 <= cx < Mc.shape[2]):
+            continue
         tgt = targets[i, rows[0]:rows[1] + 1, cols[0]:cols[1] + 1]
-        Mc[z, Y - r0, X - c0, ch] += h
-        lp = _patch_loss(O, Mc, G[i], tgt, r0, c0, rows, cols, N)
-        Mc[z, Y - r0, X - c0, ch] -= 2 * h
-        lm = _patch_loss(O, Mc, G[i], tgt, r0, c0, rows, cols, N)
+        Mc[z, cy, cx, ch] += h
+        lp = _patch_loss(O, Mc, Gc, tgt, hh, ww, N)
+        Mc[z, cy, cx, ch] -= 2 * h
+        lm = _patch_loss(O, Mc, Gc, tgt, hh, ww, N)
         total += (lp - lm) / (2 * h)
     return total
+
+
+def patch_render(O, M, G, i, rows, cols):
+    """Oracle render of view i's pixels rows x cols (inclusive ranges) of the full frame."""
+    Mc, Gc, _ = _crop_problem(M, G[i], rows, cols)
+    return O.render_view(Mc, Gc)[0][:rows[1] - rows[0] + 1, :cols[1] - cols[0] + 1]

@@ -1,17 +1,20 @@
-"""The crop-based finite differences used by the full-size gradient checks agree with the
-oracle's full-frame analytic gradient (L is quadratic in any single MPI scalar)."""
+"""The crop-based finite differences and patch renders used by the full-size checks agree
+with the oracle's full-frame analytic gradient (L is quadratic in any single MPI scalar) and
+full-frame render, for small and for large per-plane shifts."""
 
 import numpy as np
+import pytest
 
 from oracle import hsgd_oracle as O
-from tests._crop_fd import fd_scalar
+from tests._crop_fd import fd_scalar, patch_render
 from tests._problems import f32, oracle_maps, rig
 
 
-def test_crop_fd_equals_full_frame_gradient():
+@pytest.mark.parametrize("focal", [100.0, 600.0])          # shifts up to ~10 / ~60 px
+def test_crop_fd_equals_full_frame_gradient(focal):
     rng = np.random.default_rng(5)
     N, D, W, H = 3, 8, 96, 72
-    rg = rig(5, N, D, W, H, 100.0, 0.1)            # shifts up to 10 px
+    rg = rig(5, N, D, W, H, focal, 0.1)
     M = f32(rng.uniform(0.05, 0.95, size=(D, H, W, 4)))
     I = f32(rng.uniform(size=(N, H, W, 3)))
     G = oracle_maps(O, rg)
@@ -22,3 +25,17 @@ def test_crop_fd_equals_full_frame_gradient():
     for idx in picks:
         fd = fd_scalar(O, M, G, I, idx)
         assert abs(fd - g[idx]) <= 1e-8 * max(1.0, abs(g[idx])), (idx, fd, g[idx])
+
+
+def test_patch_render_equals_full_frame_render():
+    rng = np.random.default_rng(6)
+    N, D, W, H = 2, 8, 96, 72
+    rg = rig(6, N, D, W, H, 600.0, 0.1)
+    M = f32(rng.uniform(0.05, 0.95, size=(D, H, W, 4)))
+    G = oracle_maps(O, rg)
+    full = O.render(M, G)
+    for i in range(N):
+        for rows, cols in [((0, 7), (0, 9)), ((30, 41), (50, 95)), ((64, 71), (88, 95))]:
+            p = patch_render(O, M, G, i, rows, cols)
+            ref = full[i, rows[0]:rows[1] + 1, cols[0]:cols[1] + 1]
+            assert np.max(np.abs(p - ref)) <= 1e-12

@@ -261,32 +261,35 @@ def scene_inputs(name):
 
 
 def test_refine_tiny_scene_teacher_forced():
-    """Each GPU iteration of the tiny workload against the oracle step applied to the GPU's
-    own input state: ids bit-exact, updated MPI within 1e-5, loss within 1e-5 relative."""
+    """Each iteration of the tiny workload, teacher-forced by the oracle: the oracle runs its
+    own refine trajectory, and at every step the GPU starts from the oracle's state (rounded
+    to FP32, the same input both sides step from). Ids bit-exact, updated MPI within 1e-5,
+    loss within 1e-5 relative; the upsampling between levels within 1e-6."""
     sc, init, targets = scene_inputs("c1")
     plan = hsgd.RefinePlan(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths, sc.W, sc.H,
                            sc.iters, sc.k)
     pyr = O.target_pyramid(targets, sc.levels)
-    state = to_dev(init)
+    M = f32(init)                                   # the oracle's state
     for l, (w, h) in enumerate(plan.shapes):
         if l > 0:
-            prev = state.cpu().numpy().astype(np.float64)
-            state = hsgd.hsgd_upsample2x(state)
-            assert np.abs(state.cpu().numpy() - O.upsample2x(prev)).max() <= 1e-6
+            up = hsgd.hsgd_upsample2x(to_dev(M)).cpu().numpy()
+            M = f32(O.upsample2x(M))
+            assert np.abs(up - M).max() <= 1e-6
         Gl = oracle_maps(O, dict(K_ref=sc.K_ref(), K=sc.K_views(), R=sc.R_views(), t=sc.t_views(),
                                  depths=sc.depths, W=sc.W, H=sc.H), w, h)
         tl = to_dev(pyr[l])
         for _ in range(sc.iters[l]):
-            Mi = state.cpu().numpy().astype(np.float64)
+            S = O.select_active(M[..., 3], sc.k)
+            L_ref, g_ref = O.loss_and_grad(M, Gl, f32(pyr[l]))
+            nxt = f32(O.apply_update(M, g_ref, S, 1.0, 1.0))
+            state = to_dev(M)
             mask = hsgd.hsgd_select_active(state, sc.k, with_ids=False)
-            S = mask_bits(mask.cpu().numpy(), sc.D)
-            assert np.array_equal(S, O.select_active(Mi[..., 3], sc.k))
-            L_ref, g_ref = O.loss_and_grad(Mi, Gl, f32(pyr[l]))
+            assert np.array_equal(mask_bits(mask.cpu().numpy(), sc.D), S)
             _, loss = hsgd.hsgd_grad_step(state, plan.warps[l], sc.N, images=tl, mask=mask, kcap=sc.k,
                                           lr_rgb=1.0, lr_alpha=1.0, want_loss=True)
             assert abs(loss.item() - L_ref) <= 1e-5 * L_ref
-            ref = O.apply_update(Mi, g_ref, S, 1.0, 1.0)
-            assert np.abs(state.cpu().numpy() - ref).max() <= 1e-5
+            assert np.abs(state.cpu().numpy() - nxt).max() <= 1e-5
+            M = nxt
 
 
 @pytest.mark.parametrize("name", ["c1", "c2"])
@@ -303,9 +306,13 @@ def test_refine_end_to_end(name):
     np.testing.assert_allclose(losses.cpu().numpy(), ref_losses, rtol=1e-4)
     Mf = final.cpu().numpy().astype(np.float64)
     assert np.abs(Mf - M_ref).max() <= 1e-3
+    # PSNR of each side's final MPI, each rendered by its own side
     G = O.view_to_ref_maps(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths)
-    p_gpu = O.psnr(O.render(Mf, G), targets)
     p_ref = O.psnr(O.render(M_ref, G), targets)
+    table = hsgd.level_warps(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths,
+                             sc.W, sc.H, sc.W, sc.H, DEV)
+    _, L = hsgd.hsgd_render(final, table, sc.N, images=to_dev(targets), want_rgb=False, want_loss=True)
+    p_gpu = 10.0 * np.log10(1.0 / (2.0 * L.item() / (3.0 * sc.H * sc.W)))
     assert abs(p_gpu - p_ref) <= 0.01
 
 
