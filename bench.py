@@ -8,8 +8,11 @@ synthetic forward-facing scene, targets rendered by hsgd_render from the ground-
 are resident in HBM before the timed region; each step first restores the coarse initial
 MPI from a device copy (the refine updates it in place).
 
+Other workloads: --workload c5 (1920x1080, 64 planes, 8 views, 4 levels 240x135 ->
+1920x1080 with iterations [0, 1, 1, 1], k = 3, BF16 storage) and c1 (64x48x8).
+
 Prints one JSON line. value = dense-equivalent voxel-updates per refine (sum over
-iterations of D*H_l*W_l = 8,257,536) x steps / wall time of the timed region.
+iterations of D*H_l*W_l = 8,257,536 at 512x384x32) x steps / wall time of the timed region.
 """
 
 from __future__ import annotations
@@ -28,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "HSGD MPI voxel-updates/s at 512x384x32, 3 iters; p50/p99 frame latency"
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 
 def parse():
@@ -35,8 +39,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1"])
-    ap.add_argument("--dtype", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c5"],
+                    help="c2: 512x384x32 (the headline), c1: 64x48x8, c5: 1920x1080x64 8 views")
+    ap.add_argument("--dtype", default=None, choices=["fp32", "bf16"],
+                    help="MPI storage (default fp32; bf16 for c5)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run N launches of the library's plain FP32 copy kernel (256 MiB)")
@@ -64,6 +70,19 @@ def grad_launch_bytes(D, shapes, iters, N, k, s):
     return total, launches
 
 
+def grad_launch_flops(D, shapes, iters, N, k):
+    """Algorithmic FP32 operations of the gradient kernel's launches in one refine. Per
+    (view, plane, pixel) sample: the 4-tap bilinear gather of RGBA (16 mul + 12 add), the
+    over step (w = a T, C += w c, T *= 1 - a: 9), the adjoint of the over step (colour
+    r w: 3; alpha T <r, c - B>: 9; behind-composite B = a c + (1 - a) B: 9) and the
+    transposed bilinear into the active taps (4 taps x 4 channels x mul + add, on the k/D
+    active share): 58 + 32 k / D. Per view pixel the residual and loss: 12."""
+    total = 0
+    for (w, h), n in zip(shapes, iters):
+        total += n * N * w * h * (58 * D + 32 * k + 12)
+    return total
+
+
 def refine_alg_bytes(D, shapes, iters, N, k, s):
     """Algorithmic bytes of a whole refine (the method's minimum traffic): per level the
     coarse MPI read and the upsampled MPI written (l > 0); per iteration one dense MPI read,
@@ -79,7 +98,9 @@ def refine_alg_bytes(D, shapes, iters, N, k, s):
 
 
 def cpu_baseline(name):
-    """The FP64 oracle's refine of the same workload on the host, single-threaded."""
+    """The FP64 oracle on the host, single-threaded: one full refine of the same workload,
+    or, for the 1920x1080x64 frame, one finest-level iteration over a 1920x64 band of it
+    (all planes and views), reported per dense voxel-update."""
     from threadpoolctl import threadpool_limits
 
     from oracle import hsgd_oracle as O
@@ -88,16 +109,32 @@ def cpu_baseline(name):
     sc = scenes.make_scene(name)
     G = O.view_to_ref_maps(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths)
     with threadpool_limits(limits=1):
-        targets = O.render(sc.gt_mpi(), G)           # untimed input preparation
-        init = sc.initial_mpi()
-        t0 = time.perf_counter()
-        O.refine(init, targets, sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths,
-                 sc.iters, sc.k, 1.0, 1.0)
-        dt = time.perf_counter() - t0
-    dense = sum(n * sc.D * w * h for (w, h), n in zip(sc.shapes(), sc.iters))
+        if name == "c5":
+            rng = np.random.default_rng(11)
+            band = 32
+            M = scenes.random_mpi(rng, sc.D, band, sc.W, 0.05, 0.95)
+            I = scenes.random_images(rng, sc.N, band, sc.W)
+            t0 = time.perf_counter()
+            S = O.select_active(M[..., 3].astype(np.float32), sc.k)
+            _, g = O.loss_and_grad(M, G, I)
+            O.apply_update(M, g, S, 1.0, 1.0, bf16=True)
+            dt = time.perf_counter() - t0
+            dense = sc.D * band * sc.W
+            sample = (f"one finest-level iteration (select, render + loss, adjoint, BF16 update) "
+                      f"over a {sc.W}x{band} band of the {sc.W}x{sc.H}x{sc.D} frame, {sc.N} views "
+                      f"(FP64 NumPy, {dt:.1f} s), per dense voxel-update")
+        else:
+            targets = O.render(sc.gt_mpi(), G)           # untimed input preparation
+            init = sc.initial_mpi()
+            t0 = time.perf_counter()
+            O.refine(init, targets, sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths,
+                     sc.iters, sc.k, 1.0, 1.0)
+            dt = time.perf_counter() - t0
+            dense = sum(n * sc.D * w * h for (w, h), n in zip(sc.shapes(), sc.iters))
+            sample = (f"one full {len(sc.iters)}-level refine of the same {sc.W}x{sc.H}x{sc.D} scene "
+                      f"(FP64 NumPy, {dt:.1f} s; targets rendered by the oracle, untimed)")
     return {"value": dense / dt, "unit": "voxel-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"one full 3-level refine of the same {sc.W}x{sc.H}x{sc.D} scene "
-                      f"(FP64 NumPy, {dt:.1f} s; targets rendered by the oracle, untimed)"}
+            "sample": sample}
 
 
 def main():
@@ -115,14 +152,17 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     sc = scenes.make_scene(args.workload)
+    if args.dtype is None:
+        args.dtype = "bf16" if args.workload == "c5" else "fp32"
     tdtype = torch.float32 if args.dtype == "fp32" else torch.bfloat16
     s_bytes = 16 if args.dtype == "fp32" else 8
     plan = hsgd.RefinePlan(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths,
                            sc.W, sc.H, sc.iters, sc.k, lr_rgb=1.0, lr_alpha=1.0, dtype=tdtype,
                            device=dev)
-    gt = torch.from_numpy(sc.gt_mpi().astype(np.float32)).to(dev)
+    gt = torch.from_numpy(sc.gt_mpi(np.float32)).to(dev)
     targets, _ = hsgd.hsgd_render(gt, hsgd.level_warps(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(),
                                                        sc.depths, sc.W, sc.H, sc.W, sc.H, dev), sc.N)
+    del gt
     init32 = torch.from_numpy(sc.initial_mpi().astype(np.float32)).to(dev)
     init = init32 if tdtype == torch.float32 else hsgd.hsgd_convert(init32, tdtype)
     desc = plan.descriptors(targets)
@@ -164,7 +204,12 @@ def main():
         torch.cuda.synchronize()
     n_grad, ms_grad = kt.result[hsgd.K_GRAD]
     gbytes, glaunch = grad_launch_bytes(sc.D, plan.shapes, sc.iters, sc.N, sc.k, s_bytes)
-    achieved = gbytes * K / (ms_grad * 1e-3) / 1e9 if ms_grad > 0 else None
+    gflops = grad_launch_flops(sc.D, plan.shapes, sc.iters, sc.N, sc.k)
+    t_grad = ms_grad * 1e-3 / K            # gradient-kernel seconds per refine
+    achieved_gbs = gbytes / t_grad / 1e9 if ms_grad > 0 else None
+    achieved_tf = gflops / t_grad / 1e12 if ms_grad > 0 else None
+    # which roof binds: the larger of the ideal times at the HBM and the vector-ALU peaks
+    alu_bound = gflops / (FP32_VECTOR_PEAK_TFLOPS * 1e12) > gbytes / (HBM_PEAK_GBS * 1e9)
     traffic = None
     tf = os.path.join(ROOT, "profiles", f"k_grad_shift_traffic_{args.workload}_{args.dtype}.json")
     if os.path.exists(tf):
@@ -174,7 +219,8 @@ def main():
             traffic = rec.get("hbm_bytes_per_launch")
 
     out = {
-        "metric": METRIC,
+        "metric": METRIC if args.workload == "c2" else
+                  f"HSGD MPI voxel-updates/s at {sc.W}x{sc.H}x{sc.D}, {sum(sc.iters)} iters; p50/p99 frame latency",
         "value": dense * K / wall,
         "unit": "voxel-updates/s",
         "n_gpus": 1,
@@ -200,15 +246,20 @@ def main():
         "loss_log": final_loss,
         "roofline": {
             "kernel": "k_grad",
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "bound": "alu" if alu_bound else "hbm",
+            "achieved": achieved_tf if alu_bound else achieved_gbs,
+            "peak": FP32_VECTOR_PEAK_TFLOPS if alu_bound else HBM_PEAK_GBS,
+            "unit": "TFLOP/s" if alu_bound else "GB/s",
+            "frac": ((achieved_tf / FP32_VECTOR_PEAK_TFLOPS) if alu_bound else
+                     (achieved_gbs / HBM_PEAK_GBS)) if ms_grad > 0 else None,
             "traffic": traffic,
             "launches": n_grad,
             "avg_launch_us": ms_grad * 1e3 / max(n_grad, 1),
             "alg_bytes_per_launch": gbytes / glaunch,
+            "alg_flops_per_launch": gflops / glaunch,
+            "hbm": {"achieved_gbs": achieved_gbs, "frac": achieved_gbs / HBM_PEAK_GBS if achieved_gbs else None},
+            "alu": {"achieved_tflops": achieved_tf,
+                    "frac": achieved_tf / FP32_VECTOR_PEAK_TFLOPS if achieved_tf else None},
             "timing": "HIP events around every launch, separate pass of the same K steps",
         },
         "path_roofline": {

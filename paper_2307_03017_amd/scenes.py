@@ -31,6 +31,8 @@ truth are two samplings of one procedural scene.
 
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -115,8 +117,10 @@ class Scene:
         return level_shapes(self.W, self.H, self.levels)
 
     # --- rasterisation ---------------------------------------------------------------------
-    def rasterise(self, w: int, h: int) -> np.ndarray:
-        """Ground-truth MPI sampled at the pixel centres of a w x h grid: [D][h][w][4] float64."""
+    def rasterise(self, w: int, h: int, dtype=np.float64) -> np.ndarray:
+        """Ground-truth MPI sampled at the pixel centres of a w x h grid: [D][h][w][4].
+        Every value is computed in float64 (rows in chunks to bound memory) and stored in
+        ``dtype``: alpha is 0 or 1, colours are the seeds' uniform draws."""
         D = self.D
         u = (np.arange(w) + 0.5) / w
         v = (np.arange(h) + 0.5) / h
@@ -129,29 +133,55 @@ class Scene:
         fx = gx - x0
         fy = gy - y0
         g = self.grid
-        top = g[y0][:, x0] * (1 - fx)[None, :] + g[y0][:, x0 + 1] * fx[None, :]
-        bot = g[y0 + 1][:, x0] * (1 - fx)[None, :] + g[y0 + 1][:, x0 + 1] * fx[None, :]
-        inv_depth = top * (1 - fy)[:, None] + bot * fy[:, None]
         plane_inv = 1.0 / self.depths
-        dist = np.abs(inv_depth[None] - plane_inv[:, None, None])   # [D][h][w]
-        nearest = np.argmin(dist, axis=0)                            # first index wins ties
-        mpi = np.zeros((D, h, w, 4))
-        zz = np.arange(D)[:, None, None]
-        mpi[..., 3] = (zz == nearest[None]).astype(np.float64)
         aspect = self.W / self.H
         px = (u * aspect)[None, :, None]
-        py = v[:, None, None]
-        for z in range(D):
-            sx = self.seeds_xy[z, :, 0][None, None, :] * aspect
-            sy = self.seeds_xy[z, :, 1][None, None, :]
-            d2 = (px - sx) ** 2 + (py - sy) ** 2                    # [h][w][24]
-            cell = np.argmin(d2, axis=2)
-            mpi[z, :, :, :3] = self.seeds_rgb[z][cell]
+        mpi = np.zeros((D, h, w, 4), dtype=dtype)
+        zz = np.arange(D)[:, None, None]
+        rows = max(1, (1 << 20) // max(w, 1))
+        # planes are independent: large frames colour them on a few threads (NumPy releases
+        # the interpreter lock inside its array operations)
+        pool = ThreadPoolExecutor(min(8, os.cpu_count() or 1)) if w * h >= (1 << 20) else None
+        for r0 in range(0, h, rows):
+            r1 = min(h, r0 + rows)
+            ys = slice(r0, r1)
+            top = g[y0[ys]][:, x0] * (1 - fx)[None, :] + g[y0[ys]][:, x0 + 1] * fx[None, :]
+            bot = g[y0[ys] + 1][:, x0] * (1 - fx)[None, :] + g[y0[ys] + 1][:, x0 + 1] * fx[None, :]
+            inv_depth = top * (1 - fy[ys])[:, None] + bot * fy[ys][:, None]
+            dist = np.abs(inv_depth[None] - plane_inv[:, None, None])   # [D][rows][w]
+            nearest = np.argmin(dist, axis=0)                            # first index wins ties
+            mpi[:, ys, :, 3] = (zz == nearest[None])
+            dx2 = px[..., 0]                                             # [1][w]
+            dy2 = v[ys][:, None]                                         # [rows][1]
+
+            def colour_plane(z, ys=ys, nrows=r1 - r0, dx2=dx2, dy2=dy2):
+                # nearest seed; a strict comparison keeps the lower index on ties
+                best = None
+                cell = np.zeros((nrows, w), dtype=np.intp)
+                for j in range(N_VORONOI):
+                    sx = self.seeds_xy[z, j, 0] * aspect
+                    sy = self.seeds_xy[z, j, 1]
+                    d2 = (dx2 - sx) ** 2 + (dy2 - sy) ** 2
+                    if best is None:
+                        best = d2
+                    else:
+                        closer = d2 < best
+                        best = np.where(closer, d2, best)
+                        cell[closer] = j
+                mpi[z, ys, :, :3] = self.seeds_rgb[z][cell]
+
+            if pool is None:
+                for z in range(D):
+                    colour_plane(z)
+            else:
+                list(pool.map(colour_plane, range(D)))
+        if pool is not None:
+            pool.shutdown()
         return mpi
 
-    def gt_mpi(self) -> np.ndarray:
-        """Ground-truth MPI at full resolution, [D][H][W][4] float64."""
-        return self.rasterise(self.W, self.H)
+    def gt_mpi(self, dtype=np.float64) -> np.ndarray:
+        """Ground-truth MPI at full resolution, [D][H][W][4]."""
+        return self.rasterise(self.W, self.H, dtype)
 
     def initial_mpi(self) -> np.ndarray:
         """Noisy ground truth at the coarsest level, [D][h0][w0][4] float64 in [0, 1]."""
@@ -165,6 +195,23 @@ class Scene:
         out[..., :3] = c0
         out[..., 3] = a0
         return out
+
+    def noisy_mpi(self, w: int, h: int, seed: int, dtype=np.float32) -> np.ndarray:
+        """The ground truth rasterised at w x h with the initial MPI's noise model, drawn from
+        its own generator (seed): an MPI state of the kind a refinement works on, at any
+        level. Computed in ``dtype`` (float32 keeps full-frame states small)."""
+        gt = self.rasterise(w, h, dtype)
+        rng = np.random.default_rng(seed)
+        one = dtype(1.0)
+        a = np.clip(gt[..., 3], dtype(ALPHA_EPS), one - dtype(ALPHA_EPS))
+        logit = np.log(a) - np.log1p(-a)
+        logit += dtype(ALPHA_LOGIT_SIGMA) * rng.standard_normal(a.shape, dtype=dtype)
+        gt[..., 3] = one / (one + np.exp(-logit))
+        del a, logit
+        for c in range(3):
+            noise = rng.standard_normal(gt.shape[:3], dtype=dtype)
+            gt[..., c] = np.clip(gt[..., c] + dtype(COLOUR_SIGMA) * noise, 0.0, 1.0)
+        return gt
 
 
 def make_scene(name: str = "c1", seed: int | None = None, **overrides) -> Scene:
