@@ -38,9 +38,12 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c5"],
-                    help="c2: 512x384x32 (the headline), c1: 64x48x8, c5: 1920x1080x64 8 views")
+    ap.add_argument("--warmup", type=int, default=None, help="default 10 refines (100 requests for serving)")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c5", "serving"],
+                    help="c2: 512x384x32 (the headline), c1: 64x48x8, c5: 1920x1080x64 8 views, "
+                         "serving: the continuous-batching mix under Poisson arrivals")
+    ap.add_argument("--requests", type=int, default=1200, help="serving: measured requests")
+    ap.add_argument("--rate", type=float, default=60.0, help="serving: mean arrivals per second")
     ap.add_argument("--dtype", default=None, choices=["fp32", "bf16"],
                     help="MPI storage (default fp32; bf16 for c5)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -137,6 +140,79 @@ def cpu_baseline(name):
             "sample": sample}
 
 
+def serving_bench(args):
+    """Continuous batching of the 8-scene mix (256x192x16, 512x384x32, 1008x756x32; 3-5
+    views; BF16 storage): an open-loop Poisson run (latency from arrival to completion on
+    the device, after args.warmup requests), a saturated run (every request queued at
+    once: the throughput ceiling of the batch), and the batched BF16 results against the
+    plain FP32 single-request refine of the same inputs (PSNR)."""
+    import torch
+
+    from paper_2307_03017_amd import hsgd, serving
+
+    torch.cuda.set_device(0)
+    mix = serving.make_mix(variants=4)
+    snaps = {}
+
+    def snapshot(req, st):
+        key = (req.scene, req.variant)
+        if key not in snaps:
+            snaps[key] = st.result.clone()
+
+    def say(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    srv = serving.Server(mix, max_slots=8, snapshot=snapshot)
+    n = args.warmup + args.requests
+    reqs = serving.poisson_requests(n, args.rate, len(mix), 4)
+    say(f"serving: {n} requests at {args.rate} req/s")
+    done = serving.run(srv, reqs, progress=say)
+    open_loop = serving.summary(done, args.warmup, mix)
+    # saturation: all requests at t = 0
+    sat_reqs = serving.poisson_requests(400, 1e9, len(mix), 4, seed=11)
+    sat = serving.summary(serving.run(srv, sat_reqs, progress=say), 0, mix)
+    # batched BF16 vs the plain FP32 single-request refine of the same initial MPI
+    dps = []
+    for (si_i, v), res in sorted(snaps.items()):
+        si = mix[si_i]
+        sc = si.sc
+        f32, _ = hsgd.hsgd_refine(si.inits32[v], si.targets, sc.K_ref(), sc.K_views(), sc.R_views(),
+                                  sc.t_views(), sc.depths, sc.iters, sc.k)
+        table = hsgd.level_warps(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths,
+                                 sc.W, sc.H, sc.W, sc.H)
+        ps = []
+        for m in (res, f32):
+            _, L = hsgd.hsgd_render(m, table, sc.N, images=si.targets, want_rgb=False, want_loss=True)
+            ps.append(10.0 * np.log10(1.0 / (2.0 * L.item() / (3.0 * sc.H * sc.W))))
+        dps.append(abs(ps[0] - ps[1]))
+    out = {
+        "metric": f"HSGD serving p50/p99 frame latency at {args.rate:g} req/s Poisson, 8-scene mix; frames/s",
+        "value": open_loop["frames_per_s"],
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.requests,
+        "warmup": args.warmup,
+        "ms_per_step": open_loop["mean_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16-storage/f32",
+        "data": "synthetic",
+        "config": {
+            "workload": ("continuous batching, 8 persistent scenes (3x 256x192x16 k2, 3x 512x384x32 k4, "
+                         "2x 1008x756x32 k4; 3-5 views; 3 levels, 1 iteration each), BF16 MPIs resident, "
+                         "one hipGraph launch per batched iteration, 8 slots"),
+            "arrival_rate_per_s": args.rate,
+        },
+        "p50_ms": open_loop["p50_ms"],
+        "p99_ms": open_loop["p99_ms"],
+        "open_loop": open_loop,
+        "saturated": sat,
+        "bf16_batched_vs_fp32_single": {"pairs": len(dps), "max_abs_dpsnr_db": max(dps) if dps else None},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -144,6 +220,11 @@ def main():
         print("bench.py measures one GPU only: the HSGD path here has no multi-GPU "
               "implementation. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serving":
+        args.warmup = 100 if args.warmup is None else args.warmup
+        serving_bench(args)
+        return
+    args.warmup = 10 if args.warmup is None else args.warmup
 
     import torch
 

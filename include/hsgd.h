@@ -50,7 +50,8 @@ typedef enum {
     HSGD_E_DTYPE = -3,      /* unknown storage type                                    */
     HSGD_E_CAPACITY = -4,   /* output array too small (ids capacity)                   */
     HSGD_E_WORKSPACE = -5,  /* ws missing or smaller than hsgd_workspace_bytes()       */
-    HSGD_E_HIP = -6         /* a HIP runtime call or kernel launch failed              */
+    HSGD_E_HIP = -6,        /* a HIP runtime call or kernel launch failed              */
+    HSGD_E_BUDGET = -7      /* admission would exceed the serving batch's HBM budget   */
 } hsgd_status;
 
 typedef enum { HSGD_FP32 = 0, HSGD_BF16 = 1 } hsgd_dtype;
@@ -239,6 +240,93 @@ hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
  */
 hsgd_status hsgd_convert(const void* src, int32_t src_dtype, void* dst, int32_t dst_dtype,
                          size_t n, hipStream_t stream);
+
+/*
+ * Serving: continuous batching of refinements. A request is one frame of a persistent
+ * stream (scene): its views and the initial MPI at the coarsest level, refined coarse to
+ * fine exactly as hsgd_refine does. Requests that arrive while others are in flight are
+ * admitted as slots and HBM budget allow; each hsgd_batch_step runs ONE iteration of
+ * every request in flight, all of them in the same fixed sequence of persistent kernels
+ * captured once in a HIP graph (the work of each request is a range of work items in a
+ * device table rebuilt per step). A request's result is bitwise the result of hsgd_refine
+ * on the same inputs: the per-request arithmetic and its order are the same.
+ *
+ * Streams keep their buffers: the caller allocates, per stream, the MPI of every level
+ * and the images of every level (the finest holds the frame's targets, the coarser ones
+ * receive the pyramid) once and passes the same pointers with every frame; the result of
+ * a frame stays in levels[L-1] until the stream's next frame is admitted. The budget
+ * counts the batch workspace plus the resident bytes of every stream seen since it was
+ * last released (MPI levels, images, warps).
+ */
+typedef struct hsgd_batch hsgd_batch;      /* opaque */
+
+#define HSGD_MAX_BATCH_LEVELS 4
+
+typedef struct {
+    int32_t max_slots;        /* requests in flight at once, 1..16                        */
+    int32_t max_D;            /* largest plane count, <= 64                               */
+    int32_t max_N;            /* most views of a request, <= 64                           */
+    int32_t max_H, max_W;     /* largest finest-level frame                               */
+    int32_t max_k;            /* largest k of a request's selection                       */
+    int32_t dtype;            /* hsgd_dtype of every request's MPI                        */
+    int32_t pad_;
+    int64_t hbm_budget;       /* bytes: workspace + resident stream buffers               */
+} hsgd_batch_config;
+
+typedef struct {
+    int32_t stream_id;                        /* >= 0                                      */
+    int32_t L;                                /* levels, 1..HSGD_MAX_BATCH_LEVELS          */
+    hsgd_mpi levels[HSGD_MAX_BATCH_LEVELS];   /* coarsest first, each 2x the previous;     */
+                                              /* levels[0] holds the frame's initial MPI  */
+    hsgd_views views[HSGD_MAX_BATCH_LEVELS];  /* per level, shift-only warps (flag set);   */
+                                              /* images non-NULL at every level           */
+    int32_t iters[HSGD_MAX_BATCH_LEVELS];     /* >= 1, except level 0 which may be 0       */
+    hsgd_select_params sel;
+    float lr_rgb, lr_alpha;
+    float* loss_log;                          /* device [sum(iters)] FP32 or NULL          */
+} hsgd_request;
+
+/* Device workspace for hsgd_batch_create (0 for an invalid configuration). */
+size_t hsgd_batch_workspace_bytes(const hsgd_batch_config* cfg);
+
+/* Creates a batch on the current device. ws is device memory of at least
+ * hsgd_batch_workspace_bytes(cfg) bytes, owned by the caller and kept until
+ * hsgd_batch_destroy. The library allocates only host-side state, two small pinned
+ * staging buffers, events and (at the first step) the instantiated graph.
+ * HSGD_E_BUDGET if the workspace alone exceeds cfg->hbm_budget. */
+hsgd_status hsgd_batch_create(const hsgd_batch_config* cfg, void* ws, size_t ws_bytes,
+                              hsgd_batch** out);
+/* Waits for the batch's device work, then frees its host-side state. */
+hsgd_status hsgd_batch_destroy(hsgd_batch* b);
+
+/* Admits a request; *ticket identifies it. HSGD_E_CAPACITY: every slot is busy, or the
+ * stream's previous frame has iterations not yet stepped. HSGD_E_BUDGET: the stream is
+ * new and its resident bytes do not fit the remaining budget. Shapes are checked against
+ * the configuration (HSGD_E_SHAPE). Nothing runs until the next hsgd_batch_step. */
+hsgd_status hsgd_batch_admit(hsgd_batch* b, const hsgd_request* r, int64_t* ticket);
+
+/* Enqueues one iteration of every admitted request on stream (one table upload, one
+ * graph launch). Blocks the host only while the step before the previous one still holds
+ * its staging buffer. Outputs (each may be NULL): *n_active requests stepped; the tickets
+ * of requests whose last iteration this step holds, up to max_finished of them, and their
+ * number *n_finished. With no request in flight it enqueues nothing. */
+hsgd_status hsgd_batch_step(hsgd_batch* b, hipStream_t stream, int32_t* n_active,
+                            int64_t* finished, int32_t max_finished, int32_t* n_finished);
+
+/* Records the batch's time reference on stream and waits for it; completion times are
+ * measured from it. */
+hsgd_status hsgd_batch_reference(hsgd_batch* b, hipStream_t stream);
+
+/* *done = 1 once the request's last iteration has completed on the device; then
+ * *done_ms (nullable) is its completion time in ms after the reference (-1 without one). */
+hsgd_status hsgd_batch_poll(hsgd_batch* b, int64_t ticket, int32_t* done, double* done_ms);
+
+/* Forgets a stream (its resident bytes leave the budget). HSGD_E_CAPACITY while one of
+ * its frames has iterations not yet stepped. */
+hsgd_status hsgd_batch_release_stream(hsgd_batch* b, int32_t stream_id);
+
+/* Bytes currently charged to the budget (workspace + resident streams). */
+int64_t hsgd_batch_budget_used(const hsgd_batch* b);
 
 /*
  * Kernel timing (tracing). Between hsgd_profile_begin and hsgd_profile_end, every launch

@@ -37,6 +37,7 @@ SOURCES = [
     ("hsgd_api.cpp", "host"),
     ("hsgd_host.cpp", "host"),
     ("hsgd_profile.cpp", "host"),
+    ("hsgd_batch.cpp", "host"),
 ]
 
 

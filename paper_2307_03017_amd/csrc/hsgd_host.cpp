@@ -186,6 +186,7 @@ const char* hsgd_status_string(int32_t s) {
         case HSGD_E_CAPACITY: return "HSGD_E_CAPACITY: output capacity too small";
         case HSGD_E_WORKSPACE: return "HSGD_E_WORKSPACE: workspace missing or too small";
         case HSGD_E_HIP: return "HSGD_E_HIP: HIP runtime error";
+        case HSGD_E_BUDGET: return "HSGD_E_BUDGET: over the serving HBM budget";
         default: return "unknown hsgd_status";
     }
 }

@@ -114,4 +114,57 @@ int launch_upsample(const hsgd_mpi& coarse, const hsgd_mpi& fine, hipStream_t s)
 int launch_downsample(const float* img, int N, int H, int W, float* out, hipStream_t s);
 int launch_convert(const void* src, int sdt, void* dst, int ddt, size_t n, hipStream_t s);
 
+// ---- batched serving step (hsgd_batch.cpp builds the table, hsgd_kernels.hip runs it) ----
+constexpr int kMaxSlots = 16;
+constexpr int kMaxBatchLevels = 4;
+// The fixed kernel sequence of one batched step; each kernel walks a flat list of work
+// items (workgroup-sized pieces) concatenated over the slots it applies to.
+enum BatchKernel {
+    BK_DOWN0 = 0, BK_DOWN1, BK_DOWN2,            // target pyramid, finest level downwards
+    BK_UP,                                        // MPI upsampling into the current level
+    BK_SELECT,                                    // plane mask of the current level
+    BK_GRAD8, BK_GRAD16, BK_GRAD32, BK_GRAD64,    // gradient tiles, by plane-count class
+    BK_UPDATE,                                    // sparse update + loss of the iteration
+    BK_COUNT
+};
+
+// One in-flight request's work in this step (device-resident, read with scalar loads).
+struct BatchSlot {
+    void* mpi;                        // current level [D][H][W][4] (updated in place)
+    const void* up_src;               // previous level when this step upsamples into mpi
+    const float* images;              // current level targets [N][H][W][3]
+    const hsgd_warp* warps;           // current level [N][D], shift-only
+    uint64_t* mask;                   // [H][W]
+    float4* slots;                    // gradient slots [N][kcap][H][W]
+    float* partials;                  // loss partials [ntx * nty * N]
+    float* loss_out;                  // loss of this iteration (or null)
+    const float* pyr_src[kMaxBatchLevels - 1];   // pyramid stages of the first step
+    float* pyr_dst[kMaxBatchLevels - 1];
+    int pyr_h[kMaxBatchLevels - 1], pyr_w[kMaxBatchLevels - 1];   // source shapes
+    int D, H, W, N;
+    int uh, uw;                       // upsampling source shape
+    int k, kcap, ntx, nty;
+    float tau, lr_rgb, lr_alpha, pad_;
+};
+
+struct BatchTable {
+    int nslot;
+    int pad_[3];
+    int total[BK_COUNT];                       // work items per kernel
+    int pre[BK_COUNT][kMaxSlots + 1];          // per kernel: items before slot i
+    BatchSlot slot[kMaxSlots];
+};
+
+struct BatchLaunch {
+    int dtype;
+    int max_class;                 // largest plane-count class admitted (8, 16, 32 or 64)
+    int max_n, max_d;              // bound the update kernel's LDS table
+    int grid_small;                // workgroups of the 256-thread kernels
+    int grid_grad[4];              // workgroups of the gradient kernels per class
+};
+// Enqueue the fixed sequence of batched kernels reading `table` (device memory).
+int launch_batch_step(const BatchTable* table, const BatchLaunch& cfg, hipStream_t s);
+// Workgroups per CU the batched gradient kernel of a class can keep resident.
+int batch_grad_occupancy(int dtype, int cls);
+
 }  // namespace hsgd

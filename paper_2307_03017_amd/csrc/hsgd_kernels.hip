@@ -586,20 +586,22 @@ __device__ __forceinline__ float rlf(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
+// One 64 x 8 tile of one view (tile = view + N * (tx + ntx * ty)); every thread of the
+// workgroup calls it.
 template <int DT, int MAXD, bool MASKED>
-__global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
+__device__ __forceinline__ void grad_shift_tile(
     const void* __restrict__ mpi, int D, int H, int W, int N, const hsgd_warp* __restrict__ warps,
     const float* __restrict__ images, const float* __restrict__ dimg, const uint64_t* __restrict__ mask,
-    int kcap, float inv_n, float4* __restrict__ slots, float* __restrict__ partials, int ntx) {
+    int kcap, float inv_n, float4* __restrict__ slots, float* __restrict__ partials, int ntx, int tile,
+    unsigned tid) {
     __shared__ float4 s_h[2][kSX * kSY];
     __shared__ uint64_t s_bits[kSY];
     __shared__ float sred[kSX * kSY / 64];
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int view = tile % N;
     const int t2 = tile / N;
     const int tx = t2 % ntx, ty = t2 / ntx;
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int xl = tx * kOX - 1;                 // x of lane 0
     const int x = xl + lane, y = ty * kOY - 1 + wv;
     const bool ray = lane < kSX - 1 && (unsigned)x < (unsigned)W && (unsigned)y < (unsigned)H;
@@ -786,7 +788,7 @@ __global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
                 h.y = a.y * gx + lane_from_prev(a.y) * fx;
                 h.z = a.z * gx + lane_from_prev(a.z) * fx;
                 h.w = a.w * gx + lane_from_prev(a.w) * fx;
-                buf[threadIdx.x] = h;
+                buf[tid] = h;
             }
             const float oa = 1.0f - s.w;
             b0 = s.w * s.x + oa * b0;
@@ -796,7 +798,7 @@ __global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
             if ((own_bits >> z) & 1) {
                 const int rc = (int)((code[z >> 2] >> ((z & 3) * 8)) & 0xffu);
                 if (rc) {
-                    const float4 hu = buf[threadIdx.x - 64];   // the row above
+                    const float4 hu = buf[tid - 64];   // the row above
                     const float gy = 1.0f - fy;
                     float4 c;
                     c.x = h.x * gy + hu.x * fy;
@@ -816,6 +818,15 @@ __global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
     }
 }
 
+template <int DT, int MAXD, bool MASKED>
+__global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
+    const void* __restrict__ mpi, int D, int H, int W, int N, const hsgd_warp* __restrict__ warps,
+    const float* __restrict__ images, const float* __restrict__ dimg, const uint64_t* __restrict__ mask,
+    int kcap, float inv_n, float4* __restrict__ slots, float* __restrict__ partials, int ntx) {
+    grad_shift_tile<DT, MAXD, MASKED>(mpi, D, H, W, N, warps, images, dimg, mask, kcap, inv_n, slots, partials,
+                                      ntx, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x);
+}
+
 __global__ __launch_bounds__(256) void k_fill_zero(float4* __restrict__ p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -827,21 +838,23 @@ __global__ __launch_bounds__(256) void k_fill_zero(float4* __restrict__ p, int64
 // warps, view v wrote voxel (z, p) only if p lies in v's owner coverage for plane z;
 // outside it no ray of v reaches the voxel and the slot is not read. Workgroup 0 also
 // reduces the loss partials of the gradient kernel (fixed order, FP64).
+// Workgroup blk of the update over one MPI level (256 pixels); s_off is LDS for the
+// [nslices][D] shifts. Every thread of the workgroup calls it.
 template <int DT, bool SHIFT>
-__global__ __launch_bounds__(256) void k_update(void* __restrict__ mpi, int D, int H, int W,
-                                                const uint64_t* __restrict__ mask, int kcap,
-                                                const float4* __restrict__ slots, int nslices,
-                                                const hsgd_warp* __restrict__ warps, int cover_w,
-                                                int cover_h, float lr_rgb, float lr_a, int do_update,
-                                                float4* __restrict__ grad_out,
-                                                const float* __restrict__ partials, int64_t nparts,
-                                                double loss_scale, float* __restrict__ out_loss) {
-    extern __shared__ int2 s_off[];   // [nslices][D] (ix, iy) when SHIFT
+__device__ __forceinline__ void update_block(void* __restrict__ mpi, int D, int H, int W,
+                                             const uint64_t* __restrict__ mask, int kcap,
+                                             const float4* __restrict__ slots, int nslices,
+                                             const hsgd_warp* __restrict__ warps, int cover_w,
+                                             int cover_h, float lr_rgb, float lr_a, int do_update,
+                                             float4* __restrict__ grad_out,
+                                             const float* __restrict__ partials, int64_t nparts,
+                                             double loss_scale, float* __restrict__ out_loss, int blk,
+                                             int2* __restrict__ s_off) {
     if (SHIFT) {
         for (int i = threadIdx.x; i < nslices * D; i += blockDim.x) s_off[i] = make_int2(warps[i].ix, warps[i].iy);
         __syncthreads();
     }
-    if (out_loss && blockIdx.x == 0) {
+    if (out_loss && blk == 0) {
         __shared__ double sh[256];
         double acc = 0.0;
         for (int64_t i = threadIdx.x; i < nparts; i += 256) acc += (double)partials[i];
@@ -854,7 +867,7 @@ __global__ __launch_bounds__(256) void k_update(void* __restrict__ mpi, int D, i
         if (threadIdx.x == 0) *out_loss = (float)(sh[0] * loss_scale);
     }
     const int HW = H * W;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = blk * blockDim.x + threadIdx.x;
     if (p >= HW) return;
     const int Y = p / W, X = p - Y * W;
     const uint64_t m = (mask ? mask[p] : ~0ull) & plane_bits(D);
@@ -891,15 +904,28 @@ __global__ __launch_bounds__(256) void k_update(void* __restrict__ mpi, int D, i
     }
 }
 
+template <int DT, bool SHIFT>
+__global__ __launch_bounds__(256) void k_update(void* __restrict__ mpi, int D, int H, int W,
+                                                const uint64_t* __restrict__ mask, int kcap,
+                                                const float4* __restrict__ slots, int nslices,
+                                                const hsgd_warp* __restrict__ warps, int cover_w,
+                                                int cover_h, float lr_rgb, float lr_a, int do_update,
+                                                float4* __restrict__ grad_out,
+                                                const float* __restrict__ partials, int64_t nparts,
+                                                double loss_scale, float* __restrict__ out_loss) {
+    extern __shared__ int2 s_off[];   // [nslices][D] (ix, iy) when SHIFT
+    update_block<DT, SHIFT>(mpi, D, H, W, mask, kcap, slots, nslices, warps, cover_w, cover_h, lr_rgb, lr_a,
+                            do_update, grad_out, partials, nparts, loss_scale, out_loss, blockIdx.x, s_off);
+}
+
 // ------------------------------------------------------------------------------------
 // hierarchy
 // ------------------------------------------------------------------------------------
+// Output voxel i of plane z of the 2x upsampling of a [D][h][w] level.
 template <int DT>
-__global__ __launch_bounds__(256) void k_upsample(const void* __restrict__ src, int h, int w,
-                                                  void* __restrict__ dst) {
+__device__ __forceinline__ void upsample_voxel(const void* __restrict__ src, int h, int w,
+                                               void* __restrict__ dst, int z, int i) {
     const int W2 = 2 * w, H2 = 2 * h;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int z = blockIdx.y;
     if (i >= W2 * H2) return;
     const int x = i % W2, y = i / W2;
     const float sx = fminf(fmaxf((x + 0.5f) * 0.5f - 0.5f, 0.0f), (float)(w - 1));
@@ -921,17 +947,27 @@ __global__ __launch_bounds__(256) void k_upsample(const void* __restrict__ src, 
     Vox<DT>::store(dst, z * H2 * W2 + i, o);
 }
 
-__global__ __launch_bounds__(256) void k_downsample(const float* __restrict__ img, int H, int W,
-                                                    float* __restrict__ out) {
+template <int DT>
+__global__ __launch_bounds__(256) void k_upsample(const void* __restrict__ src, int h, int w,
+                                                  void* __restrict__ dst) {
+    upsample_voxel<DT>(src, h, w, dst, blockIdx.y, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Output pixel i of view n of the 2x2 box mean of [N][H][W][3] images.
+__device__ __forceinline__ void downsample_pixel(const float* __restrict__ img, int H, int W,
+                                                 float* __restrict__ out, int n, int i) {
     const int h = H / 2, w = W / 2;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int n = blockIdx.y;
     if (i >= h * w) return;
     const int x = i % w, y = i / w;
     const float* s = img + ((size_t)n * H + 2 * y) * W * 3 + 6 * x;
     float* o = out + ((size_t)n * h * w + i) * 3;
     for (int c = 0; c < 3; ++c)
         o[c] = ((s[c] + s[3 + c]) + (s[3 * W + c] + s[3 * W + 3 + c])) * 0.25f;
+}
+
+__global__ __launch_bounds__(256) void k_downsample(const float* __restrict__ img, int H, int W,
+                                                    float* __restrict__ out) {
+    downsample_pixel(img, H, W, out, blockIdx.y, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 template <int SDT, int DDT>
@@ -944,6 +980,90 @@ __global__ __launch_bounds__(256) void k_convert(const void* __restrict__ src, v
     else v = __uint_as_float((uint32_t)reinterpret_cast<const uint16_t*>(src)[i] << 16);
     if (DDT == HSGD_FP32) reinterpret_cast<float*>(dst)[i] = v;
     else reinterpret_cast<uint16_t*>(dst)[i] = (uint16_t)f32_to_bf16_bits(v);
+}
+
+// ------------------------------------------------------------------------------------
+// batched serving step: persistent kernels over the work items of every in-flight request
+// ------------------------------------------------------------------------------------
+// Slot of flat work item g of kernel kk (prefix counts are non-decreasing; uniform result).
+__device__ __forceinline__ int batch_slot_of(const BatchTable* __restrict__ t, int kk, int g) {
+    int s = 0;
+    for (int j = 1; j < t->nslot; ++j) s += g >= t->pre[kk][j] ? 1 : 0;
+    return __builtin_amdgcn_readfirstlane(s);
+}
+
+__global__ __launch_bounds__(256) void k_batch_down(const BatchTable* __restrict__ t, int stage) {
+    const int kk = BK_DOWN0 + stage;
+    const int total = t->total[kk];
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        const int sl = batch_slot_of(t, kk, g);
+        const BatchSlot& b = t->slot[sl];
+        const int j = g - t->pre[kk][sl];
+        const int H = b.pyr_h[stage], W = b.pyr_w[stage];
+        const int nb = ((H / 2) * (W / 2) + 255) / 256;
+        const int n = j / nb;
+        downsample_pixel(b.pyr_src[stage], H, W, b.pyr_dst[stage], n, (j - n * nb) * 256 + threadIdx.x);
+    }
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_batch_up(const BatchTable* __restrict__ t) {
+    const int total = t->total[BK_UP];
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        const int sl = batch_slot_of(t, BK_UP, g);
+        const BatchSlot& b = t->slot[sl];
+        const int j = g - t->pre[BK_UP][sl];
+        const int nb = (4 * b.uh * b.uw + 255) / 256;
+        const int z = j / nb;
+        upsample_voxel<DT>(b.up_src, b.uh, b.uw, b.mpi, z, (j - z * nb) * 256 + threadIdx.x);
+    }
+}
+
+template <int DT, int MAXD>
+__global__ __launch_bounds__(256) void k_batch_select(const BatchTable* __restrict__ t) {
+    const int total = t->total[BK_SELECT];
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        const int sl = batch_slot_of(t, BK_SELECT, g);
+        const BatchSlot& b = t->slot[sl];
+        const int p = (g - t->pre[BK_SELECT][sl]) * 256 + threadIdx.x;
+        const int HW = b.H * b.W;
+        if (p < HW) b.mask[p] = select_bits<DT, MAXD>(b.mpi, b.D, HW, p, b.k, b.tau);
+    }
+}
+
+// Tiles are taken in the XCD-grouped order of the flat item list (the grid is a multiple
+// of 8 workgroups), so neighbouring tiles of one request share an XCD's L2.
+template <int DT, int MAXD>
+__global__ __launch_bounds__(kSX * kSY) void k_batch_grad(const BatchTable* __restrict__ t, int kk) {
+    const int total = t->total[kk];
+    for (int i = blockIdx.x; i < total; i += gridDim.x) {
+        const int g = xcd_tile(i, total);
+        const int sl = batch_slot_of(t, kk, g);
+        const BatchSlot& b = t->slot[sl];
+        __syncthreads();                     // the previous tile's LDS reads are done
+        // a fresh copy of the thread index per tile: nothing the tile derives from it is
+        // kept live across tiles
+        unsigned tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        grad_shift_tile<DT, MAXD, true>(b.mpi, b.D, b.H, b.W, b.N, b.warps, b.images, nullptr, b.mask, b.kcap,
+                                        1.0f / (float)b.N, b.slots, b.partials, b.ntx,
+                                        g - t->pre[kk][sl], tid);
+    }
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_batch_update(const BatchTable* __restrict__ t) {
+    extern __shared__ int2 s_off[];
+    const int total = t->total[BK_UPDATE];
+    for (int g = blockIdx.x; g < total; g += gridDim.x) {
+        const int sl = batch_slot_of(t, BK_UPDATE, g);
+        const BatchSlot& b = t->slot[sl];
+        __syncthreads();                     // the previous item's shift table is no longer read
+        update_block<DT, true>(b.mpi, b.D, b.H, b.W, b.mask, b.kcap, b.slots, b.N, b.warps, b.ntx * kOX,
+                               b.nty * kOY, b.lr_rgb, b.lr_alpha, 1, nullptr, b.partials,
+                               (int64_t)b.ntx * b.nty * b.N, 0.5 / b.N, b.loss_out, g - t->pre[BK_UPDATE][sl],
+                               s_off);
+    }
 }
 
 int maxd_class(int D) { return D <= 8 ? 8 : D <= 16 ? 16 : D <= 32 ? 32 : 64; }
@@ -1107,4 +1227,37 @@ int launch_convert(const void* src, int sdt, void* dst, int ddt, size_t n, hipSt
     return (int)hipGetLastError();
 }
 
+int batch_grad_occupancy(int dtype, int cls) {
+    int n = 0;
+    hipError_t e = hipSuccess;
+    HSGD_DISPATCH_T(dtype, HSGD_DISPATCH_D(cls, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                                    &n, reinterpret_cast<const void*>(&k_batch_grad<DT, MD>),
+                                                    kSX * kSY, 0)));
+    return e == hipSuccess ? n : 0;
+}
+
+template <int DT>
+static void enqueue_batch(const BatchTable* t, const BatchLaunch& c, hipStream_t s) {
+    const dim3 small((unsigned)c.grid_small), grad(kSX * kSY);
+    for (int stage = 0; stage < kMaxBatchLevels - 1; ++stage)
+        hipLaunchKernelGGL(k_batch_down, small, dim3(256), 0, s, t, stage);
+    hipLaunchKernelGGL((k_batch_up<DT>), small, dim3(256), 0, s, t);
+    HSGD_DISPATCH_D(c.max_d, hipLaunchKernelGGL((k_batch_select<DT, MD>), small, dim3(256), 0, s, t));
+    if (c.max_class >= 8)
+        hipLaunchKernelGGL((k_batch_grad<DT, 8>), dim3((unsigned)c.grid_grad[0]), grad, 0, s, t, (int)BK_GRAD8);
+    if (c.max_class >= 16)
+        hipLaunchKernelGGL((k_batch_grad<DT, 16>), dim3((unsigned)c.grid_grad[1]), grad, 0, s, t, (int)BK_GRAD16);
+    if (c.max_class >= 32)
+        hipLaunchKernelGGL((k_batch_grad<DT, 32>), dim3((unsigned)c.grid_grad[2]), grad, 0, s, t, (int)BK_GRAD32);
+    if (c.max_class >= 64)
+        hipLaunchKernelGGL((k_batch_grad<DT, 64>), dim3((unsigned)c.grid_grad[3]), grad, 0, s, t, (int)BK_GRAD64);
+    const size_t lds = sizeof(int2) * (size_t)c.max_n * c.max_d;
+    hipLaunchKernelGGL((k_batch_update<DT>), small, dim3(256), lds, s, t);
+}
+
+int launch_batch_step(const BatchTable* t, const BatchLaunch& c, hipStream_t s) {
+    if (c.dtype == HSGD_FP32) enqueue_batch<HSGD_FP32>(t, c, s);
+    else enqueue_batch<HSGD_BF16>(t, c, s);
+    return (int)hipGetLastError();
+}
 }  // namespace hsgd

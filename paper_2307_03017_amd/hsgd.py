@@ -54,6 +54,21 @@ class SelectParams(ctypes.Structure):
 
 assert ctypes.sizeof(Warp) == 64
 
+MAX_BATCH_LEVELS = 4
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("max_D", ctypes.c_int32), ("max_N", ctypes.c_int32),
+                ("max_H", ctypes.c_int32), ("max_W", ctypes.c_int32), ("max_k", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("pad_", ctypes.c_int32), ("hbm_budget", ctypes.c_int64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("stream_id", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("levels", Mpi * MAX_BATCH_LEVELS), ("views", Views * MAX_BATCH_LEVELS),
+                ("iters", ctypes.c_int32 * MAX_BATCH_LEVELS), ("sel", SelectParams),
+                ("lr_rgb", ctypes.c_float), ("lr_alpha", ctypes.c_float), ("loss_log", ctypes.c_void_p)]
+
 # name -> (restype, argtypes); mirrors include/hsgd.h
 _P = ctypes.c_void_p
 _I = ctypes.c_int32
@@ -80,7 +95,19 @@ _SIGS = {
     "hsgd_profile_end": (_I, []),
     "hsgd_profile_read": (_I, [_I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
     "hsgd_kernel_name": (ctypes.c_char_p, [_I]),
+    "hsgd_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(BatchConfig)]),
+    "hsgd_batch_create": (_I, [ctypes.POINTER(BatchConfig), _P, ctypes.c_size_t, ctypes.POINTER(_P)]),
+    "hsgd_batch_destroy": (_I, [_P]),
+    "hsgd_batch_admit": (_I, [_P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_int64)]),
+    "hsgd_batch_step": (_I, [_P, _P, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_int64), _I,
+                             ctypes.POINTER(_I)]),
+    "hsgd_batch_reference": (_I, [_P, _P]),
+    "hsgd_batch_poll": (_I, [_P, ctypes.c_int64, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double)]),
+    "hsgd_batch_release_stream": (_I, [_P, _I]),
+    "hsgd_batch_budget_used": (ctypes.c_int64, [_P]),
 }
+
+HSGD_E_CAPACITY, HSGD_E_BUDGET = -4, -7
 
 K_SELECT, K_SCAN, K_COMPACT, K_RENDER, K_GRAD, K_UPDATE, K_FILL, K_REDUCE, K_UPSAMPLE, \
     K_DOWNSAMPLE, K_CONVERT = range(11)
@@ -418,3 +445,110 @@ def hsgd_refine(init: torch.Tensor, images: torch.Tensor, K_ref, K, R, t, depths
     plan.levels[0].copy_(init)
     plan.run(images, stream=stream)
     return plan.levels[-1], plan.loss_log[:sum(plan.iters)]
+
+
+# ---------------------------------------------------------------------------------------
+# serving: continuous batching (hsgd_batch_*)
+# ---------------------------------------------------------------------------------------
+class ServingStream:
+    """The resident device buffers of one persistent stream (scene): the MPI of every level,
+    the images of every level (the finest receives each frame's targets, the coarser ones
+    the pyramid), the per-level warp tables and a loss log. Allocated once, reused by every
+    frame of the stream."""
+
+    def __init__(self, stream_id: int, K_ref, K, R, t, depths, W: int, H: int, iters: Sequence[int], k: int,
+                 dtype: torch.dtype = torch.bfloat16, tau: float = -1.0, lr_rgb: float = 1.0,
+                 lr_alpha: float = 1.0, device="cuda"):
+        L = len(iters)
+        if L > MAX_BATCH_LEVELS:
+            raise ValueError(f"at most {MAX_BATCH_LEVELS} levels")
+        self.stream_id, self.L, self.iters, self.k = int(stream_id), L, tuple(int(i) for i in iters), int(k)
+        self.N = int(np.asarray(K).reshape(-1, 3, 3).shape[0])
+        self.D = int(len(depths))
+        self.W, self.H = W, H
+        self.shapes = [(W >> (L - 1 - l), H >> (L - 1 - l)) for l in range(L)]
+        self.warps = [level_warps(K_ref, K, R, t, depths, W, H, w, h, device) for (w, h) in self.shapes]
+        self.levels = [torch.empty((self.D, h, w, 4), dtype=dtype, device=device) for (w, h) in self.shapes]
+        self.images = [torch.empty((self.N, h, w, 3), dtype=torch.float32, device=device) for (w, h) in self.shapes]
+        self.loss_log = torch.zeros(max(1, sum(self.iters)), dtype=torch.float32, device=device)
+        req = Request()
+        req.stream_id = self.stream_id
+        req.L = L
+        for l, (w, h) in enumerate(self.shapes):
+            req.levels[l] = mpi_desc(self.levels[l])
+            req.views[l] = views_desc(self.warps[l], self.N, h, w, self.images[l])
+            req.iters[l] = self.iters[l]
+        req.sel = SelectParams(self.k, float(tau))
+        req.lr_rgb, req.lr_alpha = float(lr_rgb), float(lr_alpha)
+        req.loss_log = _ptr(self.loss_log)
+        self.request = req
+
+    @property
+    def result(self) -> torch.Tensor:
+        return self.levels[-1]
+
+
+class Batch:
+    """A continuous-batching server core on the current device (hsgd_batch_*)."""
+
+    def __init__(self, max_slots: int, max_D: int, max_N: int, max_H: int, max_W: int, max_k: int,
+                 dtype: torch.dtype = torch.bfloat16, hbm_budget: int = 1 << 40, device="cuda"):
+        self.cfg = BatchConfig(max_slots, max_D, max_N, max_H, max_W, max_k,
+                               HSGD_BF16 if dtype == torch.bfloat16 else HSGD_FP32, 0, int(hbm_budget))
+        n = lib().hsgd_batch_workspace_bytes(ctypes.byref(self.cfg))
+        if n == 0:
+            raise HsgdError(-1, f"invalid batch configuration: {lib().hsgd_last_error().decode()}")
+        self.ws = torch.empty(n, dtype=torch.uint8, device=device)
+        h = _P()
+        _check(lib().hsgd_batch_create(ctypes.byref(self.cfg), _ptr(self.ws), n, ctypes.byref(h)))
+        self.handle = h
+        self._fin = (ctypes.c_int64 * 64)()
+
+    def close(self):
+        if self.handle:
+            lib().hsgd_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def admit(self, stream: ServingStream):
+        """Ticket of the admitted frame, or None when no slot or budget is free right now
+        (HSGD_E_CAPACITY / HSGD_E_BUDGET); other errors raise."""
+        t = ctypes.c_int64()
+        st = lib().hsgd_batch_admit(self.handle, ctypes.byref(stream.request), ctypes.byref(t))
+        if st in (HSGD_E_CAPACITY, HSGD_E_BUDGET):
+            self.last_refusal = st
+            return None
+        _check(st)
+        return t.value
+
+    def step(self, stream=None):
+        """One batched iteration; returns (requests stepped, tickets that finished in it)."""
+        na, nf = _I(), _I()
+        _check(lib().hsgd_batch_step(self.handle, _stream(stream), ctypes.byref(na), self._fin, 64,
+                                     ctypes.byref(nf)))
+        return na.value, [self._fin[i] for i in range(nf.value)]
+
+    def reference(self, stream=None):
+        _check(lib().hsgd_batch_reference(self.handle, _stream(stream)))
+
+    def poll(self, ticket: int):
+        """(done, completion ms after the reference or -1)."""
+        d, ms = _I(), ctypes.c_double()
+        _check(lib().hsgd_batch_poll(self.handle, int(ticket), ctypes.byref(d), ctypes.byref(ms)))
+        return bool(d.value), ms.value
+
+    def release_stream(self, stream_id: int) -> bool:
+        st = lib().hsgd_batch_release_stream(self.handle, int(stream_id))
+        if st == HSGD_E_CAPACITY:
+            return False
+        _check(st)
+        return True
+
+    @property
+    def budget_used(self) -> int:
+        return lib().hsgd_batch_budget_used(self.handle)

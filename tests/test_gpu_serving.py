@@ -1,0 +1,147 @@
+"""Serving (continuous batching): every request's result is the same alone and in the mix.
+
+The batch core runs each request with the same per-request arithmetic as hsgd_refine, so a
+request refined in any mix, admitted at any step, must equal (bitwise: MPI and loss log)
+the same request refined alone by hsgd_refine in the same storage. The batched BF16 form
+is also compared with the plain FP32 single-request form on the same inputs: PSNR within
+0.05 dB. Admission limits (slots, one frame in flight per stream, HBM budget) are checked
+through the C-ABI's refusals.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2307_03017_amd import hsgd, serving
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+SMALL_MIX = [("s256", 100), ("s256", 101), ("s512", 103), ("s512", 104), ("s1008", 106)]
+
+
+@pytest.fixture(scope="module")
+def mix():
+    return serving.make_mix(variants=2, mix=SMALL_MIX)
+
+
+def alone(si, variant, dtype):
+    sc = si.sc
+    init = si.inits[variant] if dtype == torch.bfloat16 else si.inits32[variant]
+    return hsgd.hsgd_refine(init, si.targets, sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths,
+                            sc.iters, sc.k)
+
+
+def psnr(mpi, si):
+    sc = si.sc
+    table = hsgd.level_warps(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths, sc.W, sc.H,
+                             sc.W, sc.H, DEV)
+    _, L = hsgd.hsgd_render(mpi, table, sc.N, images=si.targets, want_rgb=False, want_loss=True)
+    return 10.0 * np.log10(1.0 / (2.0 * L.item() / (3.0 * sc.H * sc.W)))
+
+
+def test_one_request_equals_refine(mix):
+    si = mix[0]
+    srv = serving.Server([si], max_slots=2)
+    req = serving.Served(0, 1, 0.0)
+    assert srv.try_admit(req, 0.0)
+    steps = 0
+    while srv.step():
+        steps += 1
+    assert steps == sum(si.sc.iters)
+    torch.cuda.synchronize()
+    ref, ref_loss = alone(si, 1, torch.bfloat16)
+    st = srv.streams[0]
+    assert st.result.dtype == torch.bfloat16
+    assert torch.equal(st.result, ref)
+    assert torch.equal(st.loss_log[:sum(si.sc.iters)], ref_loss)
+
+
+def test_staggered_mix_each_result_equals_alone(mix):
+    """Requests of five streams (three frame sizes, two plane counts) admitted at different
+    steps, two frames for some streams (the second waits for the first): each snapshot
+    equals the request alone."""
+    snaps = {}
+
+    def snapshot(req, st):
+        snaps[req.ticket] = (req, st.result.clone(), st.loss_log.clone())
+
+    srv = serving.Server(mix, max_slots=4, snapshot=snapshot)
+    plan = {0: [(0, 0), (2, 1)], 1: [(4, 0)], 2: [(1, 1), (3, 0)], 4: [(0, 1)], 5: [(2, 0), (4, 1)]}
+    n_req = sum(len(v) for v in plan.values())
+    waiting = []
+    step = 0
+    while step < 40 and (step <= max(plan) or waiting or srv.inflight):
+        waiting += [serving.Served(s, v, float(step)) for s, v in plan.get(step, [])]
+        waiting = [r for r in waiting if not srv.try_admit(r, float(step))]
+        srv.step()
+        srv.collect(0.0)
+        step += 1
+    torch.cuda.synchronize()
+    assert len(snaps) == n_req
+    for t, (req, res, loss) in snaps.items():
+        si = mix[req.scene]
+        ref, ref_loss = alone(si, req.variant, torch.bfloat16)
+        assert torch.equal(res, ref), (si.name, req.variant)
+        n = sum(si.sc.iters)
+        assert torch.equal(loss[:n], ref_loss), (si.name, req.variant)
+
+
+def test_batched_bf16_vs_single_fp32_psnr(mix):
+    for si in mix:
+        for v in range(2):
+            f32, _ = alone(si, v, torch.float32)
+            bf, _ = alone(si, v, torch.bfloat16)
+            assert abs(psnr(f32, si) - psnr(bf, si)) <= 0.05, (si.name, v)
+
+
+def test_admission_refusals(mix):
+    srv = serving.Server(mix[:3], max_slots=2)
+    b = srv.batch
+    s0, s1, s2 = (srv._stream(i) for i in range(3))
+    t0 = b.admit(s0)
+    assert t0 is not None
+    assert b.admit(s0) is None and b.last_refusal == hsgd.HSGD_E_CAPACITY      # frame in flight
+    assert b.admit(s1) is not None
+    assert b.admit(s2) is None and b.last_refusal == hsgd.HSGD_E_CAPACITY      # slots full
+    assert not b.release_stream(0)                                            # in flight
+    while b.step()[0]:
+        pass
+    torch.cuda.synchronize()
+    assert b.poll(t0)[0]
+    used = b.budget_used
+    assert b.release_stream(0) and b.budget_used < used
+    # a budget that holds the workspace and one stream refuses a second stream
+    probe = serving.Server(mix[:2], max_slots=2)
+    ws = probe.batch.budget_used
+    assert probe.batch.admit(probe._stream(1)) is not None
+    one = probe.batch.budget_used - ws
+    assert probe.batch.admit(probe._stream(0)) is not None
+    two = probe.batch.budget_used - ws - one
+    small = serving.Server(mix[:2], max_slots=2, hbm_budget=ws + max(one, two) + 1024)
+    assert small.try_admit(serving.Served(1, 0, 0.0), 0.0)
+    assert small.batch.admit(small._stream(0)) is None and small.batch.last_refusal == hsgd.HSGD_E_BUDGET
+    # the request loop evicts the idle stream to make room
+    while small.step():
+        pass
+    assert small.try_admit(serving.Served(0, 0, 0.0), 0.0)
+    assert 1 not in small.streams
+
+
+def test_poisson_loop_latency_and_results(mix):
+    snaps = {}
+
+    def snapshot(req, st):
+        snaps[req.ticket] = (req, st.result.clone())
+
+    srv = serving.Server(mix, max_slots=8, snapshot=snapshot)
+    reqs = serving.poisson_requests(40, 60.0, len(mix), 2, seed=3)
+    done = serving.run(srv, reqs)
+    assert len(done) == 40 and len(snaps) == 40
+    s = serving.summary(done, 0, mix)
+    assert 0 < s["p50_ms"] <= s["p99_ms"] < 1000.0
+    assert all(r.done >= r.arrival for r in done)
+    for t, (req, res) in list(snaps.items())[:10]:
+        ref, _ = alone(mix[req.scene], req.variant, torch.bfloat16)
+        assert torch.equal(res, ref)
