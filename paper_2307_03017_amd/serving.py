@@ -86,16 +86,19 @@ class Server:
     """The request loop around one hsgd.Batch."""
 
     def __init__(self, inputs, max_slots: int = 8, hbm_budget: int = 64 << 30, dtype=torch.bfloat16,
-                 device="cuda", snapshot=None):
+                 device="cuda", snapshot=None, batch=None, make_stream=None):
         self.inputs = inputs
         self.dtype = dtype
         self.device = device
-        D = max(si.sc.D for si in inputs)
-        N = max(si.sc.N for si in inputs)
-        H = max(si.sc.H for si in inputs)
-        W = max(si.sc.W for si in inputs)
-        k = max(si.sc.k for si in inputs)
-        self.batch = hsgd.Batch(max_slots, D, N, H, W, k, dtype=dtype, hbm_budget=hbm_budget, device=device)
+        if batch is None:
+            D = max(si.sc.D for si in inputs)
+            N = max(si.sc.N for si in inputs)
+            H = max(si.sc.H for si in inputs)
+            W = max(si.sc.W for si in inputs)
+            k = max(si.sc.k for si in inputs)
+            batch = hsgd.Batch(max_slots, D, N, H, W, k, dtype=dtype, hbm_budget=hbm_budget, device=device)
+        self.batch = batch
+        self.make_stream = make_stream or (lambda i, si: new_stream(i, si, self.dtype, self.device))
         self.streams = {}                    # scene index -> ServingStream (resident buffers)
         self.last_used = {}
         self.snapshot = snapshot             # callable(request, stream) after a request's last step
@@ -104,7 +107,7 @@ class Server:
 
     def _stream(self, i: int) -> hsgd.ServingStream:
         if i not in self.streams:
-            self.streams[i] = new_stream(i, self.inputs[i], self.dtype, self.device)
+            self.streams[i] = self.make_stream(i, self.inputs[i])
         return self.streams[i]
 
     def try_admit(self, req: Served, now: float) -> bool:
@@ -164,20 +167,20 @@ def poisson_requests(n: int, rate: float, n_scenes: int, variants: int, seed: in
     return [Served(int(s), int(v), float(a)) for s, v, a in zip(scene, var, t)]
 
 
-def run(server: Server, reqs, warmup: int = 0, progress=None):
+def run(server: Server, reqs, warmup: int = 0, progress=None, clock=time.perf_counter, sleep=time.sleep):
     """Open-loop run: requests become visible at their arrival times (seconds after the
     start). Returns the completed requests in completion order."""
-    stream = torch.cuda.current_stream()
-    torch.cuda.synchronize()
-    server.batch.reference(stream)
-    t0 = time.perf_counter()
+    if torch.cuda.is_available():
+        torch.cuda.synchronize()
+    server.batch.reference()
+    t0 = clock()
     pending = list(reqs)
     queue = []
     done = []
     nxt = 0
     last_print = t0
     while len(done) < len(reqs):
-        now = time.perf_counter() - t0
+        now = clock() - t0
         while nxt < len(pending) and pending[nxt].arrival <= now:
             queue.append(pending[nxt])
             nxt += 1
@@ -189,19 +192,20 @@ def run(server: Server, reqs, warmup: int = 0, progress=None):
         queue = kept
         active = server.step()
         done += server.collect(0.0)           # completion times on the same origin as arrivals
-        if progress and time.perf_counter() - last_print > 5.0:
-            last_print = time.perf_counter()
+        if progress and clock() - last_print > 5.0:
+            last_print = clock()
             progress(f"serving: {len(done)}/{len(reqs)} done, {len(queue)} queued")
         if active == 0 and server.inflight:
-            time.sleep(0.0002)                # every admitted step is enqueued: wait for events
+            sleep(0.0002)                     # every admitted step is enqueued: wait for events
         elif active == 0:
             if nxt < len(pending):
-                wait = pending[nxt].arrival - (time.perf_counter() - t0)
+                wait = pending[nxt].arrival - (clock() - t0)
                 if wait > 0:
-                    time.sleep(min(wait, 0.002))
+                    sleep(min(wait, 0.002))
             elif queue:
-                time.sleep(0.0005)
-    torch.cuda.synchronize()
+                sleep(0.0005)
+    if torch.cuda.is_available():
+        torch.cuda.synchronize()
     return done
 
 

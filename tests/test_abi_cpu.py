@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     L = hsgd.lib()
-    for code in range(0, -7, -1):
+    for code in range(0, -8, -1):
         assert L.hsgd_status_string(code).decode().startswith("HSGD_")
 
 
@@ -162,3 +162,38 @@ def test_validation_status_codes():
     novs = (hsgd.Views * 2)(_views(H=8, W=8, images=None), _views(images=None))
     assert L.hsgd_refine(lv, novs, 2, it, sp(2, -1), 1.0, 1.0, None, FAKE, 1 << 30, None) == -1
     assert hsgd.lib().hsgd_last_error().decode() != ""
+
+
+def test_batch_config_validation_and_workspace_size():
+    L = hsgd.lib()
+    ok = hsgd.BatchConfig(8, 32, 5, 756, 1008, 4, hsgd.HSGD_BF16, 0, 1 << 36)
+    n8 = L.hsgd_batch_workspace_bytes(ctypes.byref(ok))
+    # per slot: plane mask, N x k gradient slices and loss partials at the largest frame
+    per_slot = 8 * 756 * 1008 + 16 * 5 * 4 * 756 * 1008
+    assert 8 * per_slot <= n8 <= 8 * per_slot + (1 << 20)
+    ok.max_slots = 4
+    assert L.hsgd_batch_workspace_bytes(ctypes.byref(ok)) < n8
+    bad = [dict(max_slots=0), dict(max_slots=17), dict(max_D=65), dict(max_k=33), dict(max_N=0),
+           dict(dtype=7), dict(hbm_budget=0), dict(max_H=1)]
+    for b in bad:
+        cfg = hsgd.BatchConfig(8, 32, 5, 756, 1008, 4, hsgd.HSGD_BF16, 0, 1 << 36)
+        for k, v in b.items():
+            setattr(cfg, k, v)
+        assert L.hsgd_batch_workspace_bytes(ctypes.byref(cfg)) == 0, b
+    assert L.hsgd_batch_workspace_bytes(None) == 0
+
+
+def test_batch_calls_reject_null_handles():
+    L = hsgd.lib()
+    t = ctypes.c_int64()
+    req = hsgd.Request()
+    assert L.hsgd_batch_admit(None, ctypes.byref(req), ctypes.byref(t)) == -1
+    assert L.hsgd_batch_step(None, None, None, None, 0, None) == -1
+    d = ctypes.c_int32()
+    assert L.hsgd_batch_poll(None, 0, ctypes.byref(d), None) == -1
+    assert L.hsgd_batch_release_stream(None, 0) == -1
+    assert L.hsgd_batch_destroy(None) == 0
+    assert L.hsgd_batch_budget_used(None) == 0
+    out = ctypes.c_void_p()
+    bad = hsgd.BatchConfig(0, 32, 5, 756, 1008, 4, hsgd.HSGD_BF16, 0, 1 << 36)
+    assert L.hsgd_batch_create(ctypes.byref(bad), FAKE, 1 << 30, ctypes.byref(out)) == -1
