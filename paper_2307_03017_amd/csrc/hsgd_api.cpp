@@ -171,8 +171,11 @@ hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
     char* inner = (char*)ws + R.inner_off;
     int it_global = 0;
     for (int l = 0; l < L; ++l) {
+        // a level's first selection comes out of the upsampling kernel that fills it
+        const bool fused = l > 0 && iters[l] > 0;
         if (l > 0) {
-            int e = launch_upsample(levels[l - 1], levels[l], stream);
+            int e = fused ? launch_upsample_select(levels[l - 1], levels[l], sel.k, sel.tau, mask, stream)
+                          : launch_upsample(levels[l - 1], levels[l], stream);
             if (e) return hip_status(e, fn);
         }
         hsgd_views v = views[l];
@@ -181,7 +184,7 @@ hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
         float4* slots = reinterpret_cast<float4*>(inner + G.slots_off);
         float* partials = reinterpret_cast<float*>(inner + G.partial_off);
         for (int it = 0; it < iters[l]; ++it, ++it_global) {
-            int e = launch_select(levels[l], sel.k, sel.tau, mask, nullptr, nullptr, stream);
+            int e = (fused && it == 0) ? 0 : launch_select(levels[l], sel.k, sel.tau, mask, nullptr, nullptr, stream);
             if (e) return hip_status(e, fn);
             e = launch_grad_step(levels[l], v, mask, sel.k, nullptr, lr_rgb, lr_alpha, nullptr,
                                  loss_log ? loss_log + it_global : nullptr, slots, partials, stream);

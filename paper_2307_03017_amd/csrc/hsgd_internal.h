@@ -111,6 +111,9 @@ int launch_grad_step(const hsgd_mpi& m, const hsgd_views& v, const uint64_t* mas
                      const float* dimg, float lr_rgb, float lr_alpha, float* grad_out, float* out_loss,
                      float4* slots, float* partials, hipStream_t s);
 int launch_upsample(const hsgd_mpi& coarse, const hsgd_mpi& fine, hipStream_t s);
+// upsampling into `fine` fused with the selection on the stored result (mask [H][W])
+int launch_upsample_select(const hsgd_mpi& coarse, const hsgd_mpi& fine, int k, float tau, uint64_t* mask,
+                           hipStream_t s);
 int launch_downsample(const float* img, int N, int H, int W, float* out, hipStream_t s);
 int launch_convert(const void* src, int sdt, void* dst, int ddt, size_t n, hipStream_t s);
 

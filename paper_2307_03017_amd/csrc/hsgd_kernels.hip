@@ -49,6 +49,14 @@ struct Vox<HSGD_FP32> {
     static __device__ __forceinline__ const char* row_ptr(const void* base, int i) {
         return reinterpret_cast<const char*>(base) + (size_t)(unsigned)i * 16;
     }
+    // voxel at byte offset `off` of a buffer resource (0 outside the resource's range)
+    static __device__ __forceinline__ float4 load_buf(__amdgpu_buffer_rsrc_t r, unsigned off) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+        return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]),
+                           __uint_as_float(v[3]));
+    }
+    static constexpr int kBytes = 16;
+    static __device__ __forceinline__ float4 stored(float4 v) { return v; }
 };
 
 template <>
@@ -75,7 +83,27 @@ struct Vox<HSGD_BF16> {
     static __device__ __forceinline__ const char* row_ptr(const void* base, int i) {
         return reinterpret_cast<const char*>(base) + (size_t)(unsigned)i * 8;
     }
+    static __device__ __forceinline__ float4 load_buf(__amdgpu_buffer_rsrc_t r, unsigned off) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        return make_float4(__uint_as_float(v[0] << 16), __uint_as_float(v[0] & 0xffff0000u),
+                           __uint_as_float(v[1] << 16), __uint_as_float(v[1] & 0xffff0000u));
+    }
+    static constexpr int kBytes = 8;
+    // the value a store followed by a load returns (round to nearest even, NaN quieted)
+    static __device__ __forceinline__ float4 stored(float4 v) {
+        return make_float4(__uint_as_float(f32_to_bf16_bits(v.x) << 16), __uint_as_float(f32_to_bf16_bits(v.y) << 16),
+                           __uint_as_float(f32_to_bf16_bits(v.z) << 16), __uint_as_float(f32_to_bf16_bits(v.w) << 16));
+    }
 };
+
+// Raw (untyped, stride 0) buffer resource over one MPI row of n_bytes bytes: loads at
+// offsets outside [0, n_bytes) return 0, which is the zero padding of a plane outside the
+// image; n_bytes = 0 makes a whole row read as padding. Word 3 selects the 32-bit data
+// format that untyped loads require on this architecture family.
+constexpr int kBufWord3 = 4 << 15;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const char* row, int n_bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(row), (short)0, n_bytes, kBufWord3);
+}
 
 // ------------------------------------------------------------------------------------
 // bilinear taps of one (view pixel, plane): zero padding, pixel-index coordinates
@@ -170,21 +198,19 @@ __device__ __forceinline__ void load_warps(hsgd_warp* sw, const hsgd_warp* warps
 // Per pixel p: A_z = fl(a_z T_z), T_{z+1} = fl(T_z fl(1 - a_z)) front to back on the
 // un-warped MPI, then the k largest A_z (equal scores: the nearer plane), then the optional
 // threshold. Returns the plane bitmask of p. FP32 contraction is off for this function.
-template <int DT, int MAXD>
-__device__ __forceinline__ uint64_t select_bits(const void* __restrict__ mpi, int D, int HW, int p,
-                                                int k, float tau) {
+// One front-to-back step of the score recursion for plane alpha a: A = fl(a T) (NaN ranks
+// last), T <- fl(T fl(1 - a)).
+__device__ __forceinline__ float score_step(float a, float& T) {
 #pragma clang fp contract(off)
-    float A[MAXD];
-    float T = 1.0f;
-#pragma unroll
-    for (int z = 0; z < MAXD; ++z) {
-        if (z < D) {
-            const float a = Vox<DT>::alpha(mpi, z * HW + p);
-            const float s = a * T;
-            A[z] = (s == s) ? s : -INFINITY;   // NaN ranks last
-            T = T * (1.0f - a);
-        }
-    }
+    const float s = a * T;
+    T = T * (1.0f - a);
+    return (s == s) ? s : -INFINITY;
+}
+
+// The plane mask of the k largest scores A[0..D) (equal scores: the nearer plane), then the
+// optional threshold.
+template <int MAXD>
+__device__ __forceinline__ uint64_t topk_bits(const float (&A)[MAXD], int D, int k, float tau) {
     const uint64_t full = D == 64 ? ~0ull : ((1ull << D) - 1);
     const int kk = min(k, D);
     uint64_t sel = 0;
@@ -225,6 +251,17 @@ __device__ __forceinline__ uint64_t select_bits(const void* __restrict__ mpi, in
             if (z < D && !(A[z] > tau)) sel &= ~(1ull << z);
     }
     return sel;
+}
+
+template <int DT, int MAXD>
+__device__ __forceinline__ uint64_t select_bits(const void* __restrict__ mpi, int D, int HW, int p,
+                                                int k, float tau) {
+    float A[MAXD];
+    float T = 1.0f;
+#pragma unroll
+    for (int z = 0; z < MAXD; ++z)
+        if (z < D) A[z] = score_step(Vox<DT>::alpha(mpi, z * HW + p), T);
+    return topk_bits<MAXD>(A, D, k, tau);
 }
 
 // The transposed view of a 64-pixel block's masks: for every plane the wave ballot (bit
@@ -630,23 +667,28 @@ __device__ __forceinline__ void grad_shift_tile(
 
     // Both scans run over MAXD planes; planes z >= D sample plane D-1 with zero weights (a
     // transparent plane) and select nothing. The taps of plane z +- kAhead are loaded while
-    // plane z is processed, and a scheduling fence per plane keeps that look-ahead (and the
-    // register footprint) fixed. The second scan samples the planes again instead of
-    // keeping them in registers: that keeps the kernel small enough for several workgroups
-    // per CU, which hides the per-plane barrier.
+    // plane z is processed (see the end of each scan), and a scheduling fence per plane
+    // keeps that look-ahead (and the register footprint) fixed. The second scan samples the
+    // planes again instead of keeping them in registers: that keeps the kernel small enough
+    // for several workgroups per CU, which hides the per-plane barrier.
     struct Taps2 {
         float4 t00, t01;   // taps of rows y0 and y0 + 1 (right-hand taps come from lane + 1)
     };
     // zstride: the plane stride HW, passed laundered to the second scan so that the
     // compiler cannot prove its loads equal the first scan's and keep those alive instead
+    // Taps come through buffer resources over the two tap rows: a column outside the
+    // plane, or a whole row outside it, reads as 0 -- the zero padding -- so neither the
+    // addresses nor the weights need per-lane range checks.
     auto fetch = [&](int z, int zstride) {
         Taps2 f;
         const int ix = rl(lx, z), iy = rl(ly, z);
         const int zb = min(z, D - 1) * zstride;
         const int Y0 = y + iy;
-        const unsigned cx = (unsigned)min(max(x + ix, 0), W - 1);
-        f.t00 = Vox<DT>::load_row(Vox<DT>::row_ptr(mpi, zb + min(max(Y0, 0), H - 1) * W), cx);
-        f.t01 = Vox<DT>::load_row(Vox<DT>::row_ptr(mpi, zb + min(max(Y0 + 1, 0), H - 1) * W), cx);
+        const int rb = W * Vox<DT>::kBytes;
+        const unsigned off = (unsigned)(x + ix) * (unsigned)Vox<DT>::kBytes;   // wraps when < 0: outside
+        const bool r0 = (unsigned)Y0 < (unsigned)H, r1 = (unsigned)(Y0 + 1) < (unsigned)H;
+        f.t00 = Vox<DT>::load_buf(row_rsrc(Vox<DT>::row_ptr(mpi, zb + (r0 ? Y0 : 0) * W), r0 ? rb : 0), off);
+        f.t01 = Vox<DT>::load_buf(row_rsrc(Vox<DT>::row_ptr(mpi, zb + (r1 ? Y0 + 1 : 0) * W), r1 ? rb : 0), off);
         return f;
     };
     // the owned cell's mask word (the tap column is the cell's column whenever the cell
@@ -660,12 +702,8 @@ __device__ __forceinline__ void grad_shift_tile(
         return *reinterpret_cast<const uint64_t*>(row + (cx << 3));
     };
     auto sample = [&](int z, const Taps2& f) {
-        const int X0 = x + rl(lx, z);
-        const float u00 = rlf(lw00, z), u10 = rlf(lw10, z), u01 = rlf(lw01, z), u11 = rlf(lw11, z);
-        const bool x0ok = (unsigned)X0 < (unsigned)W, x1ok = (unsigned)(X0 + 1) < (unsigned)W;
-        const float w00 = x0ok ? u00 : 0.0f, w01 = x0ok ? u01 : 0.0f;
-        const float w10 = x1ok ? u10 : 0.0f, w11 = x1ok ? u11 : 0.0f;
-        // the next lane's taps enter as the first FMA operand, so DPP folds into the FMA
+        const float w00 = rlf(lw00, z), w10 = rlf(lw10, z), w01 = rlf(lw01, z), w11 = rlf(lw11, z);
+        // the next lane's taps (right-hand column) come by DPP
         float4 s;
         s.x = __builtin_fmaf(lane_from_next(f.t01.x), w11, __builtin_fmaf(lane_from_next(f.t00.x), w10, __builtin_fmaf(f.t01.x, w01, f.t00.x * w00)));
         s.y = __builtin_fmaf(lane_from_next(f.t01.y), w11, __builtin_fmaf(lane_from_next(f.t00.y), w10, __builtin_fmaf(f.t01.y, w01, f.t00.y * w00)));
@@ -721,6 +759,13 @@ __device__ __forceinline__ void grad_shift_tile(
             if (__ballot(rc != 0)) own_bits |= 1ull << z;
             __builtin_amdgcn_sched_barrier(0);
         }
+        // The look-ahead loads are consumed on the path out of the loop as well, so that
+        // each is issued before its plane's branch rather than sunk to its use two planes
+        // later. Up to 32 planes that hides the load latency; with 64 planes the registers
+        // it holds cost a wave per SIMD, which loses more than it hides.
+        if constexpr (MAXD <= 32)
+            asm volatile("" ::"v"(q[0].t00.x), "v"(q[0].t01.x), "v"((uint32_t)qm[0]), "v"(q[1].t00.x),
+                         "v"(q[1].t01.x), "v"((uint32_t)qm[1]));
     }
     // planes where the wave below has selected cells: it needs this wave's adjoints
     if (lane == 0) s_bits[wv] = own_bits;
@@ -772,7 +817,6 @@ __device__ __forceinline__ void grad_shift_tile(
             const float fx = rlf(lfx, z), fy = rlf(lfy, z);
             const float4 s = sample(z, cur);
             float4* buf = s_h[z & 1];
-            float4 h = make_float4(0.f, 0.f, 0.f, 0.f);
             if ((need_bits >> z) & 1) {
                 const float Tz = Ts[z];
                 const float ca = s.w * Tz;
@@ -784,6 +828,7 @@ __device__ __forceinline__ void grad_shift_tile(
                 // horizontal half of the transposed bilinear: this ray (1 - fx) and the
                 // ray to the left (fx) both touch the owned cell's row
                 const float gx = 1.0f - fx;
+                float4 h;
                 h.x = a.x * gx + lane_from_prev(a.x) * fx;
                 h.y = a.y * gx + lane_from_prev(a.y) * fx;
                 h.z = a.z * gx + lane_from_prev(a.z) * fx;
@@ -798,7 +843,10 @@ __device__ __forceinline__ void grad_shift_tile(
             if ((own_bits >> z) & 1) {
                 const int rc = (int)((code[z >> 2] >> ((z & 3) * 8)) & 0xffu);
                 if (rc) {
-                    const float4 hu = buf[tid - 64];   // the row above
+                    // this row's and the row above's horizontal halves, both from LDS (the
+                    // own half is not kept in registers across the barrier)
+                    const float4 h = buf[tid];
+                    const float4 hu = buf[tid - 64];
                     const float gy = 1.0f - fy;
                     float4 c;
                     c.x = h.x * gy + hu.x * fy;
@@ -811,6 +859,8 @@ __device__ __forceinline__ void grad_shift_tile(
             }
             __builtin_amdgcn_sched_barrier(0);
         }
+        if constexpr (MAXD <= 32)
+            asm volatile("" ::"v"(q[0].t00.x), "v"(q[0].t01.x), "v"(q[1].t00.x), "v"(q[1].t01.x));
     }
     if (partials) {
         const float tot = block_sum(sq, sred);
@@ -922,11 +972,12 @@ __global__ __launch_bounds__(256) void k_update(void* __restrict__ mpi, int D, i
 // hierarchy
 // ------------------------------------------------------------------------------------
 // Output voxel i of plane z of the 2x upsampling of a [D][h][w] level.
+// Returns the value as stored (BF16: rounded), or 0 past the level's end.
 template <int DT>
-__device__ __forceinline__ void upsample_voxel(const void* __restrict__ src, int h, int w,
-                                               void* __restrict__ dst, int z, int i) {
+__device__ __forceinline__ float4 upsample_voxel(const void* __restrict__ src, int h, int w,
+                                                 void* __restrict__ dst, int z, int i) {
     const int W2 = 2 * w, H2 = 2 * h;
-    if (i >= W2 * H2) return;
+    if (i >= W2 * H2) return make_float4(0.f, 0.f, 0.f, 0.f);
     const int x = i % W2, y = i / W2;
     const float sx = fminf(fmaxf((x + 0.5f) * 0.5f - 0.5f, 0.0f), (float)(w - 1));
     const float sy = fminf(fmaxf((y + 0.5f) * 0.5f - 0.5f, 0.0f), (float)(h - 1));
@@ -945,12 +996,34 @@ __device__ __forceinline__ void upsample_voxel(const void* __restrict__ src, int
     o.z = w00 * a.z + w10 * b.z + w01 * c.z + w11 * d.z;
     o.w = w00 * a.w + w10 * b.w + w01 * c.w + w11 * d.w;
     Vox<DT>::store(dst, z * H2 * W2 + i, o);
+    return Vox<DT>::stored(o);
 }
 
 template <int DT>
 __global__ __launch_bounds__(256) void k_upsample(const void* __restrict__ src, int h, int w,
                                                   void* __restrict__ dst) {
     upsample_voxel<DT>(src, h, w, dst, blockIdx.y, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Upsampling fused with the first selection at the new level: one thread per output pixel
+// writes its D voxels and scores the alpha it stored (the storage-rounded value), so the
+// mask equals what k_select computes from the stored level.
+template <int DT, int MAXD>
+__global__ __launch_bounds__(256) void k_upsample_select(const void* __restrict__ src, int D, int h, int w,
+                                                         void* __restrict__ dst, int k, float tau,
+                                                         uint64_t* __restrict__ mask) {
+    const int W2 = 2 * w, H2 = 2 * h;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= W2 * H2) return;
+    float A[MAXD];
+    float T = 1.0f;
+#pragma unroll
+    for (int z = 0; z < MAXD; ++z) {
+        if (z < D) {
+            A[z] = score_step(upsample_voxel<DT>(src, h, w, dst, z, i).w, T);
+        }
+    }
+    mask[i] = topk_bits<MAXD>(A, D, k, tau);
 }
 
 // Output pixel i of view n of the 2x2 box mean of [N][H][W][3] images.
@@ -1203,6 +1276,14 @@ int launch_upsample(const hsgd_mpi& c, const hsgd_mpi& f, hipStream_t s) {
     const dim3 grid((unsigned)ceil_div((int64_t)f.H * f.W, 256), (unsigned)c.D);
     ProfScope ps(HSGD_K_UPSAMPLE, s);
     HSGD_DISPATCH_T(c.dtype, hipLaunchKernelGGL((k_upsample<DT>), grid, dim3(256), 0, s, c.rgba, c.H, c.W, f.rgba));
+    return (int)hipGetLastError();
+}
+
+int launch_upsample_select(const hsgd_mpi& c, const hsgd_mpi& f, int k, float tau, uint64_t* mask, hipStream_t s) {
+    const dim3 grid((unsigned)ceil_div((int64_t)f.H * f.W, 256));
+    ProfScope ps(HSGD_K_UPSAMPLE, s);
+    HSGD_DISPATCH_T(c.dtype, HSGD_DISPATCH_D(c.D, hipLaunchKernelGGL((k_upsample_select<DT, MD>), grid, dim3(256), 0, s,
+                                                                    c.rgba, c.D, c.H, c.W, f.rgba, k, tau, mask)));
     return (int)hipGetLastError();
 }
 
