@@ -634,6 +634,9 @@ __device__ __forceinline__ void grad_shift_tile(
     __shared__ float4 s_h[2][kSX * kSY];
     __shared__ uint64_t s_bits[kSY];
     __shared__ float sred[kSX * kSY / 64];
+    __shared__ float4 s_w[kSY][MAXD];                       // per wave row and plane: tap weights
+    __shared__ float2 s_f[MAXD];                            // per plane: the shift's fraction
+    __shared__ uint32_t s_code[(MAXD + 3) / 4][kSX * kSY];  // rank bytes of 4 planes per thread
     const int view = tile % N;
     const int t2 = tile / N;
     const int tx = t2 % ntx, ty = t2 / ntx;
@@ -646,24 +649,28 @@ __device__ __forceinline__ void grad_shift_tile(
     const int HW = H * W;
     const uint64_t full = plane_bits(D);
 
-    // lane z < D holds plane z's shift and its four bilinear weights for this wave's row
-    // (taps in rows outside the plane already zeroed); lanes z >= D hold zeros
+    // Plane tables. Lane z < D holds plane z's integer shift (read per plane with
+    // v_readlane: it feeds scalar address arithmetic). The four bilinear weights of each
+    // plane for this wave's row (taps in rows outside the plane zeroed) and the shift's
+    // fraction go to LDS, read per plane as broadcasts. Planes z >= D get zeros.
     int lx = 0, ly = 0;
-    float lw00 = 0.0f, lw10 = 0.0f, lw01 = 0.0f, lw11 = 0.0f, lfx = 0.0f, lfy = 0.0f;
-    if (lane < D) {
-        const hsgd_warp& w = warps[(size_t)view * D + lane];
-        lx = w.ix;
-        ly = w.iy;
-        lfx = w.fx;
-        lfy = w.fy;
-        const int Y0 = y + ly;
-        const float gy = (unsigned)Y0 < (unsigned)H ? 1.0f - lfy : 0.0f;
-        const float hy = (unsigned)(Y0 + 1) < (unsigned)H ? lfy : 0.0f;
-        lw00 = (1.0f - lfx) * gy;
-        lw10 = lfx * gy;
-        lw01 = (1.0f - lfx) * hy;
-        lw11 = lfx * hy;
+    if (lane < MAXD) {
+        float4 wt = make_float4(0.f, 0.f, 0.f, 0.f);
+        float2 fr = make_float2(0.f, 0.f);
+        if (lane < D) {
+            const hsgd_warp& w = warps[(size_t)view * D + lane];
+            lx = w.ix;
+            ly = w.iy;
+            fr = make_float2(w.fx, w.fy);
+            const int Y0 = y + ly;
+            const float gy = (unsigned)Y0 < (unsigned)H ? 1.0f - fr.y : 0.0f;
+            const float hy = (unsigned)(Y0 + 1) < (unsigned)H ? fr.y : 0.0f;
+            wt = make_float4((1.0f - fr.x) * gy, fr.x * gy, (1.0f - fr.x) * hy, fr.x * hy);
+        }
+        s_w[wv][lane] = wt;
+        if (wv == 0) s_f[lane] = fr;
     }
+    __syncthreads();
 
     // Both scans run over MAXD planes; planes z >= D sample plane D-1 with zero weights (a
     // transparent plane) and select nothing. The taps of plane z +- kAhead are loaded while
@@ -702,7 +709,8 @@ __device__ __forceinline__ void grad_shift_tile(
         return *reinterpret_cast<const uint64_t*>(row + (cx << 3));
     };
     auto sample = [&](int z, const Taps2& f) {
-        const float w00 = rlf(lw00, z), w10 = rlf(lw10, z), w01 = rlf(lw01, z), w11 = rlf(lw11, z);
+        const float4 wt = s_w[wv][z];
+        const float w00 = wt.x, w10 = wt.y, w01 = wt.z, w11 = wt.w;
         // the next lane's taps (right-hand column) come by DPP
         float4 s;
         s.x = __builtin_fmaf(lane_from_next(f.t01.x), w11, __builtin_fmaf(lane_from_next(f.t00.x), w10, __builtin_fmaf(f.t01.x, w01, f.t00.x * w00)));
@@ -718,10 +726,9 @@ __device__ __forceinline__ void grad_shift_tile(
     int go = 1;
 
     float Ts[MAXD];
-    uint32_t code[(MAXD + 3) / 4];               // per plane: rank + 1 of the owned cell, or 0
+    uint32_t code = 0;                           // rank + 1 of the owned cell (or 0) per plane,
+                                                 // 4 planes per word, flushed to s_code
     uint64_t own_bits = 0;                       // planes where an owned cell of this wave is selected
-#pragma unroll
-    for (int i = 0; i < (MAXD + 3) / 4; ++i) code[i] = 0;
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
     {
         Taps2 q[kAhead];
@@ -755,7 +762,11 @@ __device__ __forceinline__ void grad_shift_tile(
             const uint32_t sel = cell ? (uint32_t)((m >> z) & 1) : 0u;
             const uint32_t rank = (uint32_t)__popcll(m & ((1ull << z) - 1));
             const uint32_t rc = (sel && rank < (uint32_t)kcap) ? rank + 1 : 0u;
-            code[z >> 2] |= rc << ((z & 3) * 8);
+            code |= rc << ((z & 3) * 8);
+            if ((z & 3) == 3 || z == MAXD - 1) {
+                s_code[z >> 2][tid] = code;
+                code = 0;
+            }
             if (__ballot(rc != 0)) own_bits |= 1ull << z;
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -801,7 +812,8 @@ __device__ __forceinline__ void grad_shift_tile(
     // launder what the second scan derives its taps from, so that nothing computed per
     // plane in the first scan is kept alive for it
     int HW2 = HW;
-    asm volatile("" : "+s"(HW2), "+v"(lx), "+v"(ly), "+v"(lw00), "+v"(lw10), "+v"(lw01), "+v"(lw11));
+    asm volatile("" : "+s"(HW2), "+v"(lx), "+v"(ly));
+    uint32_t rcode = 0;
     {
         Taps2 q[kAhead];
 #pragma unroll
@@ -814,7 +826,9 @@ __device__ __forceinline__ void grad_shift_tile(
             if (!__builtin_amdgcn_readfirstlane(go)) break;
             const Taps2 cur = q[zz % kAhead];
             if (zz + kAhead < MAXD) q[zz % kAhead] = fetch(z - kAhead, HW2);
-            const float fx = rlf(lfx, z), fy = rlf(lfy, z);
+            const float2 fr = s_f[z];
+            const float fx = fr.x, fy = fr.y;
+            if ((z & 3) == 3 || z == MAXD - 1) rcode = s_code[z >> 2][tid];
             const float4 s = sample(z, cur);
             float4* buf = s_h[z & 1];
             if ((need_bits >> z) & 1) {
@@ -841,7 +855,7 @@ __device__ __forceinline__ void grad_shift_tile(
             b2 = s.w * s.z + oa * b2;
             __syncthreads();
             if ((own_bits >> z) & 1) {
-                const int rc = (int)((code[z >> 2] >> ((z & 3) * 8)) & 0xffu);
+                const int rc = (int)((rcode >> ((z & 3) * 8)) & 0xffu);
                 if (rc) {
                     // this row's and the row above's horizontal halves, both from LDS (the
                     // own half is not kept in registers across the barrier)
@@ -868,8 +882,10 @@ __device__ __forceinline__ void grad_shift_tile(
     }
 }
 
+// Up to 32 planes the kernel is held to 6 waves per SIMD (3 workgroups per CU): the
+// occupancy gained outweighs the one or two registers that spill.
 template <int DT, int MAXD, bool MASKED>
-__global__ __launch_bounds__(kSX * kSY) void k_grad_shift(
+__global__ __launch_bounds__(kSX * kSY) __attribute__((amdgpu_waves_per_eu(MAXD <= 32 ? 6 : 1))) void k_grad_shift(
     const void* __restrict__ mpi, int D, int H, int W, int N, const hsgd_warp* __restrict__ warps,
     const float* __restrict__ images, const float* __restrict__ dimg, const uint64_t* __restrict__ mask,
     int kcap, float inv_n, float4* __restrict__ slots, float* __restrict__ partials, int ntx) {
