@@ -253,14 +253,19 @@ __device__ __forceinline__ uint64_t topk_bits(const float (&A)[MAXD], int D, int
     return sel;
 }
 
+// All D alpha loads are issued before the first is used (plane index clamped, so the loads
+// need no guard): one memory latency per pixel rather than one per plane.
 template <int DT, int MAXD>
 __device__ __forceinline__ uint64_t select_bits(const void* __restrict__ mpi, int D, int HW, int p,
                                                 int k, float tau) {
+    float a[MAXD];
+#pragma unroll
+    for (int z = 0; z < MAXD; ++z) a[z] = Vox<DT>::alpha(mpi, min(z, D - 1) * HW + p);
     float A[MAXD];
     float T = 1.0f;
 #pragma unroll
     for (int z = 0; z < MAXD; ++z)
-        if (z < D) A[z] = score_step(Vox<DT>::alpha(mpi, z * HW + p), T);
+        if (z < D) A[z] = score_step(a[z], T);
     return topk_bits<MAXD>(A, D, k, tau);
 }
 
@@ -937,18 +942,32 @@ __device__ __forceinline__ void update_block(void* __restrict__ mpi, int D, int 
     if (p >= HW) return;
     const int Y = p / W, X = p - Y * W;
     const uint64_t m = (mask ? mask[p] : ~0ull) & plane_bits(D);
+    // Sum of the view slices of rank r (plane z). The loads of 8 views are issued together
+    // (view index clamped; a view whose owners do not cover the cell, or past the last, is
+    // skipped by a select, never by arithmetic: its slot holds stale data); the sum runs in
+    // view order.
     auto grad_of = [&](int z, int r) {
         float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int v = 0; v < nslices; ++v) {
-            if (SHIFT) {
-                const int2 o = s_off[v * D + z];
-                if ((unsigned)(X - o.x) >= (unsigned)cover_w || (unsigned)(Y - o.y) >= (unsigned)cover_h) continue;
+        for (int v0 = 0; v0 < nslices; v0 += 8) {
+            float4 t[8];
+            bool ok[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int v = min(v0 + j, nslices - 1);
+                ok[j] = v0 + j < nslices;
+                if (SHIFT) {
+                    const int2 o = s_off[v * D + z];
+                    ok[j] = ok[j] && (unsigned)(X - o.x) < (unsigned)cover_w && (unsigned)(Y - o.y) < (unsigned)cover_h;
+                }
+                t[j] = slots[((size_t)v * kcap + r) * HW + p];
             }
-            const float4 t = slots[((size_t)v * kcap + r) * HW + p];
-            g.x += t.x;
-            g.y += t.y;
-            g.z += t.z;
-            g.w += t.w;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                g.x += ok[j] ? t[j].x : 0.0f;
+                g.y += ok[j] ? t[j].y : 0.0f;
+                g.z += ok[j] ? t[j].z : 0.0f;
+                g.w += ok[j] ? t[j].w : 0.0f;
+            }
         }
         return g;
     };
@@ -957,10 +976,11 @@ __device__ __forceinline__ void update_block(void* __restrict__ mpi, int D, int 
     while (b && r < kcap) {
         const int z = __ffsll((unsigned long long)b) - 1;
         b &= b - 1;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (do_update) v = Vox<DT>::load(mpi, z * HW + p);     // in flight with the slices
         const float4 g = grad_of(z, r++);
         if (grad_out) grad_out[(size_t)z * HW + p] = g;
         if (do_update) {
-            float4 v = Vox<DT>::load(mpi, z * HW + p);
             v.x = fminf(fmaxf(v.x - lr_rgb * g.x, 0.0f), 1.0f);
             v.y = fminf(fmaxf(v.y - lr_rgb * g.y, 0.0f), 1.0f);
             v.z = fminf(fmaxf(v.z - lr_rgb * g.z, 0.0f), 1.0f);
@@ -988,12 +1008,16 @@ __global__ __launch_bounds__(256) void k_update(void* __restrict__ mpi, int D, i
 // hierarchy
 // ------------------------------------------------------------------------------------
 // Output voxel i of plane z of the 2x upsampling of a [D][h][w] level.
-// Returns the value as stored (BF16: rounded), or 0 past the level's end.
+// The four source taps of output voxel i of a 2x upsampling (plane base z*h*w of the
+// source) and their weights.
 template <int DT>
-__device__ __forceinline__ float4 upsample_voxel(const void* __restrict__ src, int h, int w,
-                                                 void* __restrict__ dst, int z, int i) {
-    const int W2 = 2 * w, H2 = 2 * h;
-    if (i >= W2 * H2) return make_float4(0.f, 0.f, 0.f, 0.f);
+struct UpTaps {
+    float4 a, b, c, d;
+    float w00, w10, w01, w11;
+};
+template <int DT>
+__device__ __forceinline__ UpTaps<DT> upsample_taps(const void* __restrict__ src, int h, int w, int z, int i) {
+    const int W2 = 2 * w;
     const int x = i % W2, y = i / W2;
     const float sx = fminf(fmaxf((x + 0.5f) * 0.5f - 0.5f, 0.0f), (float)(w - 1));
     const float sy = fminf(fmaxf((y + 0.5f) * 0.5f - 0.5f, 0.0f), (float)(h - 1));
@@ -1001,18 +1025,39 @@ __device__ __forceinline__ float4 upsample_voxel(const void* __restrict__ src, i
     const int x1 = min(x0 + 1, w - 1), y1 = min(y0 + 1, h - 1);
     const float fx = sx - x0, fy = sy - y0;
     const int base = z * h * w;
-    const float4 a = Vox<DT>::load(src, base + y0 * w + x0);
-    const float4 b = Vox<DT>::load(src, base + y0 * w + x1);
-    const float4 c = Vox<DT>::load(src, base + y1 * w + x0);
-    const float4 d = Vox<DT>::load(src, base + y1 * w + x1);
-    const float w00 = (1 - fx) * (1 - fy), w10 = fx * (1 - fy), w01 = (1 - fx) * fy, w11 = fx * fy;
+    UpTaps<DT> t;
+    t.a = Vox<DT>::load(src, base + y0 * w + x0);
+    t.b = Vox<DT>::load(src, base + y0 * w + x1);
+    t.c = Vox<DT>::load(src, base + y1 * w + x0);
+    t.d = Vox<DT>::load(src, base + y1 * w + x1);
+    t.w00 = (1 - fx) * (1 - fy);
+    t.w10 = fx * (1 - fy);
+    t.w01 = (1 - fx) * fy;
+    t.w11 = fx * fy;
+    return t;
+}
+
+// Blends the taps, stores output voxel i of plane z and returns the value as stored (BF16:
+// rounded).
+template <int DT>
+__device__ __forceinline__ float4 upsample_store(const UpTaps<DT>& t, void* __restrict__ dst, int H2W2, int z,
+                                                 int i) {
     float4 o;
-    o.x = w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x;
-    o.y = w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y;
-    o.z = w00 * a.z + w10 * b.z + w01 * c.z + w11 * d.z;
-    o.w = w00 * a.w + w10 * b.w + w01 * c.w + w11 * d.w;
-    Vox<DT>::store(dst, z * H2 * W2 + i, o);
+    o.x = t.w00 * t.a.x + t.w10 * t.b.x + t.w01 * t.c.x + t.w11 * t.d.x;
+    o.y = t.w00 * t.a.y + t.w10 * t.b.y + t.w01 * t.c.y + t.w11 * t.d.y;
+    o.z = t.w00 * t.a.z + t.w10 * t.b.z + t.w01 * t.c.z + t.w11 * t.d.z;
+    o.w = t.w00 * t.a.w + t.w10 * t.b.w + t.w01 * t.c.w + t.w11 * t.d.w;
+    Vox<DT>::store(dst, z * H2W2 + i, o);
     return Vox<DT>::stored(o);
+}
+
+// Output voxel i of plane z of the 2x upsampling of a [D][h][w] level; returns the value
+// as stored, or 0 past the level's end.
+template <int DT>
+__device__ __forceinline__ float4 upsample_voxel(const void* __restrict__ src, int h, int w,
+                                                 void* __restrict__ dst, int z, int i) {
+    if (i >= 4 * w * h) return make_float4(0.f, 0.f, 0.f, 0.f);
+    return upsample_store<DT>(upsample_taps<DT>(src, h, w, z, i), dst, 4 * w * h, z, i);
 }
 
 template <int DT>
@@ -1033,11 +1078,17 @@ __global__ __launch_bounds__(256) void k_upsample_select(const void* __restrict_
     if (i >= W2 * H2) return;
     float A[MAXD];
     float T = 1.0f;
+    // planes in groups of 4: the group's 16 tap loads are in flight together (plane index
+    // clamped, so they need no guard)
+    constexpr int kG = 4;
 #pragma unroll
-    for (int z = 0; z < MAXD; ++z) {
-        if (z < D) {
-            A[z] = score_step(upsample_voxel<DT>(src, h, w, dst, z, i).w, T);
-        }
+    for (int z0 = 0; z0 < MAXD; z0 += kG) {
+        UpTaps<DT> t[kG];
+#pragma unroll
+        for (int j = 0; j < kG; ++j) t[j] = upsample_taps<DT>(src, h, w, min(z0 + j, D - 1), i);
+#pragma unroll
+        for (int j = 0; j < kG; ++j)
+            if (z0 + j < D) A[z0 + j] = score_step(upsample_store<DT>(t[j], dst, W2 * H2, z0 + j, i).w, T);
     }
     mask[i] = topk_bits<MAXD>(A, D, k, tau);
 }
