@@ -608,11 +608,13 @@ constexpr int kOX = kShiftOX, kOY = kShiftOY;
 static_assert(kOX == kSX - 2, "lanes: halo, owners, tap supplier");
 
 // DPP wave shifts (bound_ctrl: a lane without a source reads 0)
-__device__ __forceinline__ float lane_from_next(float v) {   // lane i <- lane i+1 (63 <- 0)
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xF, 0xF, true));
+// Lane i <- lane i+1 (lane 63 <- 0) and lane i <- lane i-1 (lane 0 <- 0), written so that
+// the shift folds into the consuming add or multiply as a DPP operand.
+__device__ __forceinline__ float lane_from_next(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
 }
-__device__ __forceinline__ float lane_from_prev(float v) {   // lane i <- lane i-1 (0 <- 0)
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xF, 0xF, true));
+__device__ __forceinline__ float lane_from_prev(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
 }
 
 // Block index -> tile index so that each XCD (workgroups are dealt round-robin to the 8
@@ -716,12 +718,13 @@ __device__ __forceinline__ void grad_shift_tile(
     auto sample = [&](int z, const Taps2& f) {
         const float4 wt = s_w[wv][z];
         const float w00 = wt.x, w10 = wt.y, w01 = wt.z, w11 = wt.w;
-        // the next lane's taps (right-hand column) come by DPP
+        // left column of both tap rows from this lane; the right column's weighted sum is
+        // formed by the next lane on its own taps and added through DPP
         float4 s;
-        s.x = __builtin_fmaf(lane_from_next(f.t01.x), w11, __builtin_fmaf(lane_from_next(f.t00.x), w10, __builtin_fmaf(f.t01.x, w01, f.t00.x * w00)));
-        s.y = __builtin_fmaf(lane_from_next(f.t01.y), w11, __builtin_fmaf(lane_from_next(f.t00.y), w10, __builtin_fmaf(f.t01.y, w01, f.t00.y * w00)));
-        s.z = __builtin_fmaf(lane_from_next(f.t01.z), w11, __builtin_fmaf(lane_from_next(f.t00.z), w10, __builtin_fmaf(f.t01.z, w01, f.t00.z * w00)));
-        s.w = __builtin_fmaf(lane_from_next(f.t01.w), w11, __builtin_fmaf(lane_from_next(f.t00.w), w10, __builtin_fmaf(f.t01.w, w01, f.t00.w * w00)));
+        s.x = __builtin_fmaf(f.t01.x, w01, f.t00.x * w00) + lane_from_next(__builtin_fmaf(f.t01.x, w11, f.t00.x * w10));
+        s.y = __builtin_fmaf(f.t01.y, w01, f.t00.y * w00) + lane_from_next(__builtin_fmaf(f.t01.y, w11, f.t00.y * w10));
+        s.z = __builtin_fmaf(f.t01.z, w01, f.t00.z * w00) + lane_from_next(__builtin_fmaf(f.t01.z, w11, f.t00.z * w10));
+        s.w = __builtin_fmaf(f.t01.w, w01, f.t00.w * w00) + lane_from_next(__builtin_fmaf(f.t01.w, w11, f.t00.w * w10));
         return s;
     };
     constexpr int kAhead = 2;
@@ -848,10 +851,10 @@ __device__ __forceinline__ void grad_shift_tile(
                 // ray to the left (fx) both touch the owned cell's row
                 const float gx = 1.0f - fx;
                 float4 h;
-                h.x = a.x * gx + lane_from_prev(a.x) * fx;
-                h.y = a.y * gx + lane_from_prev(a.y) * fx;
-                h.z = a.z * gx + lane_from_prev(a.z) * fx;
-                h.w = a.w * gx + lane_from_prev(a.w) * fx;
+                h.x = __builtin_fmaf(a.x, gx, lane_from_prev(a.x) * fx);
+                h.y = __builtin_fmaf(a.y, gx, lane_from_prev(a.y) * fx);
+                h.z = __builtin_fmaf(a.z, gx, lane_from_prev(a.z) * fx);
+                h.w = __builtin_fmaf(a.w, gx, lane_from_prev(a.w) * fx);
                 buf[tid] = h;
             }
             const float oa = 1.0f - s.w;
@@ -942,31 +945,36 @@ __device__ __forceinline__ void update_block(void* __restrict__ mpi, int D, int 
     if (p >= HW) return;
     const int Y = p / W, X = p - Y * W;
     const uint64_t m = (mask ? mask[p] : ~0ull) & plane_bits(D);
-    // Sum of the view slices of rank r (plane z). The loads of 8 views are issued together
-    // (view index clamped; a view whose owners do not cover the cell, or past the last, is
-    // skipped by a select, never by arithmetic: its slot holds stale data); the sum runs in
-    // view order.
+    // Sum of the view slices of rank r (plane z), in view order. The loads of 8 views are
+    // issued together through one buffer resource per view slice: a view whose owners do
+    // not cover the cell (its slot holds stale data), or past the last view, gets an offset
+    // outside the resource and reads 0 without touching memory.
+    const unsigned slice_bytes = (unsigned)kcap * (unsigned)HW * 16u;
     auto grad_of = [&](int z, int r) {
         float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+        const unsigned off = ((unsigned)r * (unsigned)HW + (unsigned)p) * 16u;
         for (int v0 = 0; v0 < nslices; v0 += 8) {
             float4 t[8];
-            bool ok[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int v = min(v0 + j, nslices - 1);
-                ok[j] = v0 + j < nslices;
+                bool ok = v0 + j < nslices;
                 if (SHIFT) {
                     const int2 o = s_off[v * D + z];
-                    ok[j] = ok[j] && (unsigned)(X - o.x) < (unsigned)cover_w && (unsigned)(Y - o.y) < (unsigned)cover_h;
+                    ok = ok && (unsigned)(X - o.x) < (unsigned)cover_w && (unsigned)(Y - o.y) < (unsigned)cover_h;
                 }
-                t[j] = slots[((size_t)v * kcap + r) * HW + p];
+                const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                    const_cast<float4*>(slots + (size_t)v * kcap * HW), (short)0, (int)slice_bytes, kBufWord3);
+                const auto u = __builtin_amdgcn_raw_buffer_load_b128(rs, ok ? off : 0xfffffff0u, 0, 0);
+                t[j] = make_float4(__uint_as_float(u[0]), __uint_as_float(u[1]), __uint_as_float(u[2]),
+                                   __uint_as_float(u[3]));
             }
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                g.x += ok[j] ? t[j].x : 0.0f;
-                g.y += ok[j] ? t[j].y : 0.0f;
-                g.z += ok[j] ? t[j].z : 0.0f;
-                g.w += ok[j] ? t[j].w : 0.0f;
+                g.x += t[j].x;
+                g.y += t[j].y;
+                g.z += t[j].z;
+                g.w += t[j].w;
             }
         }
         return g;
