@@ -116,7 +116,9 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, copy_k
 def traffic_md(t, cmd: str) -> str:
     out = ["# HBM traffic per launch", "", "Commands:", "", "```", cmd, "```", "",
            f"Calibration with the library's plain FP32 copy kernel over a buffer of known size: "
-           f"FETCH_SIZE x {t['fetch_factor']:.3f}, WRITE_SIZE x {t['write_factor']:.3f}.", "",
+           f"FETCH_SIZE x {t['fetch_factor']:.3f}, WRITE_SIZE x {t['write_factor']:.3f}. "
+           "Both counters count what leaves L2 towards memory: reads that the Infinity Cache "
+           "serves are included.", "",
            f"Kernel source hash: `{t['kernel_source_hash']}`", "",
            "| kernel | grid | read MB | write MB |", "|---|---:|---:|---:|"]
     for l in t["launches"]:
