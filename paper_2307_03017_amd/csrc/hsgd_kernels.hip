@@ -687,6 +687,7 @@ __device__ __forceinline__ void grad_shift_tile(
     // for several workgroups per CU, which hides the per-plane barrier.
     struct Taps2 {
         float4 t00, t01;   // taps of rows y0 and y0 + 1 (right-hand taps come from lane + 1)
+        int ix, iy;        // the plane's integer shift (wave-uniform), carried with its taps
     };
     // zstride: the plane stride HW, passed laundered to the second scan so that the
     // compiler cannot prove its loads equal the first scan's and keep those alive instead
@@ -696,6 +697,8 @@ __device__ __forceinline__ void grad_shift_tile(
     auto fetch = [&](int z, int zstride) {
         Taps2 f;
         const int ix = rl(lx, z), iy = rl(ly, z);
+        f.ix = ix;
+        f.iy = iy;
         const int zb = min(z, D - 1) * zstride;
         const int Y0 = y + iy;
         const int rb = W * Vox<DT>::kBytes;
@@ -705,15 +708,16 @@ __device__ __forceinline__ void grad_shift_tile(
         f.t01 = Vox<DT>::load_buf(row_rsrc(Vox<DT>::row_ptr(mpi, zb + (r1 ? Y0 + 1 : 0) * W), r1 ? rb : 0), off);
         return f;
     };
-    // the owned cell's mask word (the tap column is the cell's column whenever the cell
-    // lies inside the plane)
-    auto fetch_mask = [&](int z) -> uint64_t {
+    // the owned cell's mask word (the tap column is the cell's column), through a buffer
+    // resource over the cell's mask row: a cell outside the plane reads 0, i.e. unselected
+    auto fetch_mask = [&](const Taps2& f) -> uint64_t {
         if (!MASKED) return full;
-        const int ix = rl(lx, z), iy = rl(ly, z);
-        const int Y = min(max(y + iy, 0), H - 1);
-        const unsigned cx = (unsigned)min(max(x + ix, 0), W - 1);
-        const char* row = reinterpret_cast<const char*>(mask) + (size_t)(unsigned)(Y * W) * 8;
-        return *reinterpret_cast<const uint64_t*>(row + (cx << 3));
+        const int Y = y + f.iy;
+        const bool rv = (unsigned)Y < (unsigned)H;
+        const char* row = reinterpret_cast<const char*>(mask) + (size_t)(unsigned)((rv ? Y : 0) * W) * 8;
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(row_rsrc(row, rv ? W * 8 : 0),
+                                                            (unsigned)(x + f.ix) * 8u, 0, 0);
+        return ((uint64_t)v[1] << 32) | v[0];
     };
     auto sample = [&](int z, const Taps2& f) {
         const float4 wt = s_w[wv][z];
@@ -745,7 +749,7 @@ __device__ __forceinline__ void grad_shift_tile(
         for (int i = 0; i < kAhead; ++i)
             if (i < MAXD) {
                 q[i] = fetch(i, HW);
-                qm[i] = fetch_mask(i);
+                qm[i] = fetch_mask(q[i]);
             }
 #pragma unroll
         for (int z = 0; z < MAXD; ++z) {
@@ -755,7 +759,7 @@ __device__ __forceinline__ void grad_shift_tile(
             const uint64_t m = qm[z % kAhead];
             if (z + kAhead < MAXD) {
                 q[z % kAhead] = fetch(z + kAhead, HW);
-                qm[z % kAhead] = fetch_mask(z + kAhead);
+                qm[z % kAhead] = fetch_mask(q[z % kAhead]);
             }
             const float4 s = sample(z, cur);
             Ts[z] = T;
@@ -764,8 +768,9 @@ __device__ __forceinline__ void grad_shift_tile(
             c1 += wgt * s.y;
             c2 += wgt * s.z;
             T *= 1.0f - s.w;
-            const int Y = y + rl(ly, z), X = x + rl(lx, z);
-            const bool cell = owner && z < D && (unsigned)Y < (unsigned)H && (unsigned)X < (unsigned)W;
+            // (a cell outside the plane has a zero mask word; without a mask, check the range)
+            const bool cell = owner && z < D &&
+                              (MASKED || ((unsigned)(y + cur.iy) < (unsigned)H && (unsigned)(x + cur.ix) < (unsigned)W));
             // branch-free: rank + 1 of the owned cell's plane z if selected, else 0
             const uint32_t sel = cell ? (uint32_t)((m >> z) & 1) : 0u;
             const uint32_t rank = (uint32_t)__popcll(m & ((1ull << z) - 1));
@@ -875,7 +880,7 @@ __device__ __forceinline__ void grad_shift_tile(
                     c.y = h.y * gy + hu.y * fy;
                     c.z = h.z * gy + hu.z * fy;
                     c.w = h.w * gy + hu.w * fy;
-                    const unsigned idx = (unsigned)((rc - 1) * HW + (y + rl(ly, z)) * W + (x + rl(lx, z)));
+                    const unsigned idx = (unsigned)((rc - 1) * HW + (y + cur.iy) * W + (x + cur.ix));
                     *reinterpret_cast<float4*>(reinterpret_cast<char*>(vslots) + (idx << 4)) = c;
                 }
             }
