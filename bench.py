@@ -39,9 +39,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=None, help="default 10 refines (100 requests for serving)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c5", "serving"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c5", "serving", "views18"],
                     help="c2: 512x384x32 (the headline), c1: 64x48x8, c5: 1920x1080x64 8 views, "
-                         "serving: the continuous-batching mix under Poisson arrivals")
+                         "serving: the continuous-batching mix under Poisson arrivals, "
+                         "views18: 18 novel views of a refined 512x384x32 MPI per step")
     ap.add_argument("--requests", type=int, default=1200, help="serving: measured requests")
     ap.add_argument("--rate", type=float, default=60.0, help="serving: mean arrivals per second")
     ap.add_argument("--dtype", default=None, choices=["fp32", "bf16"],
@@ -213,6 +214,125 @@ def serving_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def novel_rig(sc, cols=6, rows=3, a=0.1):
+    """cols x rows novel view positions on a grid in [-a, a] x [-a/2, a/2]."""
+    xs = np.linspace(-a, a, cols)
+    ys = np.linspace(-a / 2, a / 2, rows)
+    t = np.array([[x, y, 0.0] for y in ys for x in xs])
+    N = len(t)
+    return np.repeat(sc.K_ref()[None], N, axis=0), np.repeat(np.eye(3)[None], N, axis=0), t
+
+
+def views_bench(args):
+    """Novel-view rendering of a built MPI: the 512x384x32 scene refined as in the headline
+    (FP32 or BF16 storage), then per step one hsgd_render of 18 views on a 6x3 grid (the
+    view set a light-field display consumes), outputs [18][384][512][3] FP32."""
+    import torch
+
+    from paper_2307_03017_amd import hsgd, scenes
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    sc = scenes.make_scene("c2")
+    tdtype = torch.float32 if args.dtype == "fp32" else torch.bfloat16
+    s_bytes = 16 if args.dtype == "fp32" else 8
+    gt = torch.from_numpy(sc.gt_mpi(np.float32)).to(dev)
+    table = hsgd.level_warps(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths,
+                             sc.W, sc.H, sc.W, sc.H, dev)
+    targets, _ = hsgd.hsgd_render(gt, table, sc.N)
+    init = torch.from_numpy(sc.initial_mpi().astype(np.float32)).to(dev)
+    if tdtype != torch.float32:
+        init = hsgd.hsgd_convert(init, tdtype)
+    mpi, _ = hsgd.hsgd_refine(init, targets, sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(),
+                              sc.depths, sc.iters, sc.k)
+    K, R, t = novel_rig(sc)
+    nv = len(t)
+    novel = hsgd.level_warps(sc.K_ref(), K, R, t, sc.depths, sc.W, sc.H, sc.W, sc.H, dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        hsgd.hsgd_render(mpi, novel, nv)
+    torch.cuda.synchronize()
+    steps = args.steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[i][0].record(stream)
+        hsgd.hsgd_render(mpi, novel, nv)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    with hsgd.KernelTimer([hsgd.K_RENDER]) as kt:
+        for _ in range(steps):
+            hsgd.hsgd_render(mpi, novel, nv)
+        torch.cuda.synchronize()
+    n_r, ms_r = kt.result[hsgd.K_RENDER]
+    HW = sc.H * sc.W
+    alg_bytes = sc.D * HW * s_bytes + nv * HW * 12
+    alg_flops = nv * HW * (37 * sc.D)           # per sample: bilinear RGBA 28, over step 9
+    t_launch = ms_r * 1e-3 / max(n_r, 1)
+    gbs = alg_bytes / t_launch / 1e9
+    tfl = alg_flops / t_launch / 1e12
+    alu_bound = alg_flops / (FP32_VECTOR_PEAK_TFLOPS * 1e12) > alg_bytes / (HBM_PEAK_GBS * 1e9)
+    out = {
+        "metric": "novel views/s rendered from a refined 512x384x32 MPI (18-view sets); p50/p99 set latency",
+        "value": nv * steps / wall,
+        "unit": "views/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.dtype == "fp32" else "bf16-storage/f32",
+        "data": "synthetic",
+        "config": {"workload": (f"hsgd_render of {nv} translated views (6x3 grid, +-0.1 x, +-0.05 y) of the "
+                                f"refined {sc.W}x{sc.H}x{sc.D} MPI, {args.dtype} storage"),
+                   "views_per_step": nv},
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "view_sets_per_s": steps / wall,
+        "roofline": {
+            "kernel": "k_render_shift",
+            "bound": "alu" if alu_bound else "hbm",
+            "achieved": tfl if alu_bound else gbs,
+            "peak": FP32_VECTOR_PEAK_TFLOPS if alu_bound else HBM_PEAK_GBS,
+            "unit": "TFLOP/s" if alu_bound else "GB/s",
+            "frac": (tfl / FP32_VECTOR_PEAK_TFLOPS) if alu_bound else (gbs / HBM_PEAK_GBS),
+            "traffic": None,
+            "launches": n_r,
+            "avg_launch_us": t_launch * 1e6,
+            "alg_bytes_per_launch": alg_bytes,
+            "alg_flops_per_launch": alg_flops,
+            "hbm": {"achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS},
+            "alu": {"achieved_tflops": tfl, "frac": tfl / FP32_VECTOR_PEAK_TFLOPS},
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = views_cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+def views_cpu_baseline():
+    """The FP64 oracle rendering 3 of the novel views at full size, single-threaded."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import hsgd_oracle as O
+    from paper_2307_03017_amd import scenes
+
+    sc = scenes.make_scene("c2")
+    K, R, t = novel_rig(sc)
+    G = O.view_to_ref_maps(sc.K_ref(), K[:3], R[:3], t[:3], sc.depths)
+    M = sc.noisy_mpi(sc.W, sc.H, seed=77).astype(np.float64)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        O.render(M, G)
+        dt = time.perf_counter() - t0
+    return {"value": 3 / dt, "unit": "views/s", "cores": 1, "kind": "oracle",
+            "sample": f"3 of the 18 novel views of a {sc.W}x{sc.H}x{sc.D} MPI (FP64 NumPy, {dt:.1f} s)"}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -225,6 +345,10 @@ def main():
         serving_bench(args)
         return
     args.warmup = 10 if args.warmup is None else args.warmup
+    if args.workload == "views18":
+        args.dtype = args.dtype or "fp32"
+        views_bench(args)
+        return
 
     import torch
 

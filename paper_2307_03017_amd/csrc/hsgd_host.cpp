@@ -103,7 +103,10 @@ ActiveSet active_at(void* ws, const ActiveLayout& L, int* ids, int* nact) {
 
 RenderWs render_ws(int H, int W, int N) {
     RenderWs w{};
-    w.nparts = ceil_div(W, kTileW) * ceil_div(H, kTileH) * N;
+    // loss partials of either render kernel: general (64 x 4 rays) or translation (63 x 8)
+    const int64_t general = ceil_div(W, kTileW) * ceil_div(H, kTileH) * N;
+    const int64_t shift = ceil_div(W, kShiftRX) * ceil_div(H, kShiftRY) * N;
+    w.nparts = general > shift ? general : shift;
     w.partial_off = 0;
     w.bytes = align_up(sizeof(float) * w.nparts);
     return w;

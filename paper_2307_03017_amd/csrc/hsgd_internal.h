@@ -20,6 +20,10 @@ constexpr int kBlock = kTileW * kTileH;
 // Shift-warp gradient blocks: 64 x 8 lanes of which 62 x 7 own a reference cell per plane.
 constexpr int kShiftOX = 62;
 constexpr int kShiftOY = 7;
+// Translation-warp render workgroups: 64 x 8 lanes of which 63 x 8 are rays (lane 63 only
+// supplies the right-hand taps of lane 62).
+constexpr int kShiftRX = 63;
+constexpr int kShiftRY = 8;
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -906,6 +906,112 @@ __global__ __launch_bounds__(kSX * kSY) __attribute__((amdgpu_waves_per_eu(MAXD 
                                       ntx, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x);
 }
 
+// ------------------------------------------------------------------------------------
+// render, translation warps: the gradient kernel's front-to-back scan on its own
+// ------------------------------------------------------------------------------------
+// One workgroup = 63 x 8 rays of one view (lane 63 of each wave only supplies the right-
+// hand taps of lane 62): per plane two row loads through buffer resources (hardware zero
+// padding), per-wave tap weights from an LDS table, the right column through DPP, two
+// planes of loads in flight.
+template <int DT, int MAXD>
+__global__ __launch_bounds__(kSX * kSY) void k_render_shift(const void* __restrict__ mpi, int D, int H, int W,
+                                                            int N, const hsgd_warp* __restrict__ warps,
+                                                            const float* __restrict__ images,
+                                                            float* __restrict__ out_rgb,
+                                                            float* __restrict__ partials, int ntx) {
+    __shared__ float4 s_w[kSY][MAXD];
+    __shared__ float sred[kSX * kSY / 64];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int view = tile % N;
+    const int t2 = tile / N;
+    const int tx = t2 % ntx, ty = t2 / ntx;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int xl = tx * kShiftRX;
+    const int x = xl + lane, y = ty * kShiftRY + wv;
+    const bool ray = lane < kShiftRX && x < W && y < H;
+    int lx = 0, ly = 0;
+    if (lane < MAXD) {
+        float4 wt = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (lane < D) {
+            const hsgd_warp& w = warps[(size_t)view * D + lane];
+            lx = w.ix;
+            ly = w.iy;
+            const int Y0 = y + ly;
+            const float gy = (unsigned)Y0 < (unsigned)H ? 1.0f - w.fy : 0.0f;
+            const float hy = (unsigned)(Y0 + 1) < (unsigned)H ? w.fy : 0.0f;
+            wt = make_float4((1.0f - w.fx) * gy, w.fx * gy, (1.0f - w.fx) * hy, w.fx * hy);
+        }
+        s_w[wv][lane] = wt;
+    }
+    __syncthreads();
+    const int HW = H * W;
+    const int rb = W * Vox<DT>::kBytes;
+    struct Taps2 {
+        float4 t00, t01;
+    };
+    auto fetch = [&](int z) {
+        Taps2 f;
+        const int ix = rl(lx, z), iy = rl(ly, z);
+        const int zb = min(z, D - 1) * HW;
+        const int Y0 = y + iy;
+        const unsigned off = (unsigned)(x + ix) * (unsigned)Vox<DT>::kBytes;
+        const bool r0 = (unsigned)Y0 < (unsigned)H, r1 = (unsigned)(Y0 + 1) < (unsigned)H;
+        f.t00 = Vox<DT>::load_buf(row_rsrc(Vox<DT>::row_ptr(mpi, zb + (r0 ? Y0 : 0) * W), r0 ? rb : 0), off);
+        f.t01 = Vox<DT>::load_buf(row_rsrc(Vox<DT>::row_ptr(mpi, zb + (r1 ? Y0 + 1 : 0) * W), r1 ? rb : 0), off);
+        return f;
+    };
+    constexpr int kAhead = 2;
+    int go = 1;
+    float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+    {
+        Taps2 q[kAhead];
+#pragma unroll
+        for (int i = 0; i < kAhead; ++i)
+            if (i < MAXD) q[i] = fetch(i);
+#pragma unroll
+        for (int z = 0; z < MAXD; ++z) {
+            asm volatile("" : "+v"(go));
+            if (!__builtin_amdgcn_readfirstlane(go)) break;
+            const Taps2 f = q[z % kAhead];
+            if (z + kAhead < MAXD) q[z % kAhead] = fetch(z + kAhead);
+            const float4 wt = s_w[wv][z];
+            float4 s;
+            s.x = __builtin_fmaf(f.t01.x, wt.z, f.t00.x * wt.x) + lane_from_next(__builtin_fmaf(f.t01.x, wt.w, f.t00.x * wt.y));
+            s.y = __builtin_fmaf(f.t01.y, wt.z, f.t00.y * wt.x) + lane_from_next(__builtin_fmaf(f.t01.y, wt.w, f.t00.y * wt.y));
+            s.z = __builtin_fmaf(f.t01.z, wt.z, f.t00.z * wt.x) + lane_from_next(__builtin_fmaf(f.t01.z, wt.w, f.t00.z * wt.y));
+            s.w = __builtin_fmaf(f.t01.w, wt.z, f.t00.w * wt.x) + lane_from_next(__builtin_fmaf(f.t01.w, wt.w, f.t00.w * wt.y));
+            const float wgt = T * s.w;
+            c0 += wgt * s.x;
+            c1 += wgt * s.y;
+            c2 += wgt * s.z;
+            T *= 1.0f - s.w;
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // keep the look-ahead loads ahead of each plane's branch (see the gradient kernel)
+        asm volatile("" ::"v"(q[0].t00.x), "v"(q[0].t01.x), "v"(q[1].t00.x), "v"(q[1].t01.x));
+    }
+    float sq = 0.0f;
+    if (ray) {
+        const size_t pix = ((size_t)view * H + y) * W + x;
+        if (out_rgb) {
+            out_rgb[3 * pix + 0] = c0;
+            out_rgb[3 * pix + 1] = c1;
+            out_rgb[3 * pix + 2] = c2;
+        }
+        if (partials) {
+            const float d0 = c0 - images[3 * pix + 0];
+            const float d1 = c1 - images[3 * pix + 1];
+            const float d2 = c2 - images[3 * pix + 2];
+            sq = d0 * d0 + d1 * d1 + d2 * d2;
+        }
+    }
+    if (partials) {
+        const float tot = block_sum(sq, sred);
+        if (threadIdx.x == 0) partials[tile] = tot;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_fill_zero(float4* __restrict__ p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1272,15 +1378,25 @@ int launch_render(const hsgd_mpi& m, const hsgd_views& v, float* out_rgb, float*
                   void* ws, hipStream_t s) {
     const RenderWs L = render_ws(m.H, m.W, v.N);
     float* partials = out_loss ? reinterpret_cast<float*>((char*)ws + L.partial_off) : nullptr;
-    const dim3 grid((unsigned)ceil_div(m.W, kTileW), (unsigned)ceil_div(m.H, kTileH), (unsigned)v.N);
-    {
+    int64_t nparts;
+    if (v.flags & HSGD_VIEWS_SHIFT_ONLY) {
+        const int ntx = (int)ceil_div(m.W, kShiftRX), nty = (int)ceil_div(m.H, kShiftRY);
+        nparts = (int64_t)ntx * nty * v.N;
+        ProfScope ps(HSGD_K_RENDER, s);
+        HSGD_DISPATCH_T(m.dtype, HSGD_DISPATCH_D(m.D, hipLaunchKernelGGL((k_render_shift<DT, MD>), dim3((unsigned)nparts),
+                                                                        dim3(kSX * kSY), 0, s, m.rgba, m.D, m.H, m.W,
+                                                                        v.N, v.warps, v.images, out_rgb, partials,
+                                                                        ntx)));
+    } else {
+        const dim3 grid((unsigned)ceil_div(m.W, kTileW), (unsigned)ceil_div(m.H, kTileH), (unsigned)v.N);
+        nparts = (int64_t)grid.x * grid.y * grid.z;
         ProfScope ps(HSGD_K_RENDER, s);
         HSGD_DISPATCH_T(m.dtype, hipLaunchKernelGGL((k_render<DT>), grid, dim3(kBlock), 0, s, m.rgba, m.D,
                                                     m.H, m.W, v.warps, v.images, out_rgb, partials));
     }
     if (out_loss) {
         ProfScope ps(HSGD_K_REDUCE, s);
-        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, L.nparts, 0.5 / v.N, out_loss);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, nparts, 0.5 / v.N, out_loss);
     }
     return (int)hipGetLastError();
 }

@@ -1,0 +1,75 @@
+"""Novel-view rendering of a built MPI (the display step after refinement: a light-field
+display needs 18 views at once): hsgd_render with 18 translated views of a 512x384x32 MPI
+through the translation render kernel, against the FP64 oracle -- whole frames for some
+views, patches (with the frame's borders) for all -- in FP32 and BF16 storage, and against
+the library's general-warp render of the same views."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import hsgd_oracle as O
+from paper_2307_03017_amd import hsgd, scenes
+from tests._crop_fd import patch_render
+from tests._problems import f32
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def novel_rig(sc, cols=6, rows=3, a=0.1):
+    """cols x rows view positions on a grid in [-a, a] x [-a/2, a/2] (identity rotation)."""
+    xs = np.linspace(-a, a, cols)
+    ys = np.linspace(-a / 2, a / 2, rows)
+    t = np.array([[x, y, 0.0] for y in ys for x in xs])
+    N = len(t)
+    K = np.repeat(sc.K_ref()[None], N, axis=0)
+    R = np.repeat(np.eye(3)[None], N, axis=0)
+    return K, R, t
+
+
+@pytest.fixture(scope="module")
+def views():
+    sc = scenes.make_scene("c2")
+    M = f32(sc.noisy_mpi(sc.W, sc.H, seed=77))
+    K, R, t = novel_rig(sc)
+    G = O.view_to_ref_maps(sc.K_ref(), K, R, t, sc.depths)
+    table = hsgd.level_warps(sc.K_ref(), K, R, t, sc.depths, sc.W, sc.H, sc.W, sc.H, DEV)
+    assert table.shift_only and table.N == 18
+    return sc, M, G, table
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16], ids=["fp32", "bf16"])
+def test_eighteen_views_match_oracle(views, dtype):
+    sc, M, G, table = views
+    Mq = M if dtype == torch.float32 else f32(O.bf16_round(M))
+    out, _ = hsgd.hsgd_render(torch.from_numpy(M).to(DEV).to(dtype), table, 18)
+    C = out.cpu().numpy()
+    for i in (0, 17):                                   # the grid's corners, whole frames
+        ref = O.render_view(Mq, G[i])[0]
+        assert np.abs(C[i] - ref).max() <= 1e-5
+    rng = np.random.default_rng(9)
+    for i in range(18):
+        for y0, x0 in [(0, 0), (sc.H - 8, sc.W - 16)] + [(int(rng.integers(0, sc.H - 8)),
+                                                         int(rng.integers(0, sc.W - 16))) for _ in range(2)]:
+            ref = patch_render(O, Mq, G, i, (y0, y0 + 7), (x0, x0 + 15))
+            assert np.abs(C[i, y0:y0 + 8, x0:x0 + 16] - ref).max() <= 1e-5
+
+
+def test_translation_render_equals_general_render(views):
+    sc, M, G, table = views
+    Md = torch.from_numpy(M).to(DEV).float()
+    a, _ = hsgd.hsgd_render(Md, table, 18)
+    b, _ = hsgd.hsgd_render(Md, table.tensor, 18)       # raw records: the general-warp kernel
+    assert (a - b).abs().max().item() <= 5e-5
+
+
+def test_render_loss_on_translation_path(views):
+    sc, M, G, table = views
+    rng = np.random.default_rng(10)
+    I = rng.uniform(size=(18, sc.H, sc.W, 3)).astype(np.float32)
+    out, L = hsgd.hsgd_render(torch.from_numpy(M).to(DEV).float(), table, 18,
+                              images=torch.from_numpy(I).to(DEV), want_loss=True)
+    own = float(np.sum((out.cpu().numpy().astype(np.float64) - I) ** 2) / 36.0)
+    assert abs(L.item() - own) <= 1e-5 * own
