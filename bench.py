@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--rate", type=float, default=60.0, help="serving: mean arrivals per second")
     ap.add_argument("--dtype", default=None, choices=["fp32", "bf16"],
                     help="MPI storage (default fp32; bf16 for c5)")
+    ap.add_argument("--rule", default="topk", choices=["topk", "mvs"],
+                    help="sparsification: the paper's top-k by alpha gradient, or the MVS-sampling window")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run N launches of the library's plain FP32 copy kernel (256 MiB)")
@@ -363,7 +365,7 @@ def main():
     s_bytes = 16 if args.dtype == "fp32" else 8
     plan = hsgd.RefinePlan(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths,
                            sc.W, sc.H, sc.iters, sc.k, lr_rgb=1.0, lr_alpha=1.0, dtype=tdtype,
-                           device=dev)
+                           device=dev, rule=args.rule)
     gt = torch.from_numpy(sc.gt_mpi(np.float32)).to(dev)
     targets, _ = hsgd.hsgd_render(gt, hsgd.level_warps(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(),
                                                        sc.depths, sc.W, sc.H, sc.W, sc.H, dev), sc.N)
@@ -440,7 +442,8 @@ def main():
         "config": {
             "workload": (f"hsgd_refine {sc.W}x{sc.H}x{sc.D} planes, {sc.N} views, "
                          f"{len(sc.iters)} levels {'->'.join(f'{w}x{h}' for w, h in plan.shapes)}, "
-                         f"iters {list(sc.iters)}, k={sc.k}, {args.dtype} storage"),
+                         f"iters {list(sc.iters)}, k={sc.k}, {args.dtype} storage"
+                         + ("" if args.rule == "topk" else ", MVS-sampling selection")),
             "dense_voxel_updates_per_refine": dense,
             "active_voxel_updates_per_refine": active,
         },

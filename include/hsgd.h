@@ -90,11 +90,20 @@ typedef struct {
     int32_t flags;
 } hsgd_views;
 
-/* Sparsification rule. k: planes kept per pixel (1..D). tau < 0: pure top-k (the paper's
- * rule); tau >= 0 additionally drops planes whose score A_z <= tau. */
+/* Sparsification rule (Sec. 3.3 "Gradient Sparsification"), on the scores A_z of the
+ * un-warped MPI. k: planes kept per pixel (1..D).
+ *  rule HSGD_SELECT_TOPK (0, the paper's rule): the k largest A_z, equal scores to the
+ *       nearer plane;
+ *  rule HSGD_SELECT_MVS (1, the MVS-sampling alternative the paper ablates): the plane with
+ *       the largest A_z (equal scores: the nearer) and its neighbours, (k - 1)/2 planes
+ *       nearer (rounded down) and the rest farther; a window that would leave [0, D) is
+ *       moved inside it, so k planes are always kept.
+ * tau < 0: nothing more; tau >= 0 additionally drops kept planes whose A_z <= tau. */
+enum { HSGD_SELECT_TOPK = 0, HSGD_SELECT_MVS = 1 };
 typedef struct {
     int32_t k;
     float tau;
+    int32_t rule;
 } hsgd_select_params;
 
 /* Operation codes for hsgd_workspace_bytes. */
@@ -226,7 +235,7 @@ hsgd_status hsgd_downsample2x(const float* images, int32_t N, int32_t H, int32_t
  *          finest level required; images of a coarser level may be NULL, in which case
  *          they are computed as 2x2 box means of the next finer level into the workspace.
  *  iters   host [L] iterations per level (>= 0).
- *  sel     sparsification rule (k, tau) used at every iteration.
+ *  sel     sparsification rule (k, tau, rule) used at every iteration.
  *  loss_log device [sum(iters)] FP32 or NULL: loss of each iteration before its update.
  */
 hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,

@@ -247,15 +247,27 @@ def select_scores_f32(alpha):
     return A
 
 
-def select_active(alpha, k, tau=-1.0):
-    """Per pixel, the k planes with the largest A (equal A: the nearer plane first); with
-    tau >= 0 planes whose A <= tau are dropped too. Returns a bool mask [D][H][W]."""
+def select_active(alpha, k, tau=-1.0, rule="topk"):
+    """Per pixel, the planes kept by the sparsification rule (Sec. 3.3), as a bool mask
+    [D][H][W]. "topk" (the paper's rule): the k planes with the largest A (equal A: the
+    nearer plane first). "mvs" (the MVS-sampling alternative the paper ablates): the plane
+    with the largest A (equal A: the nearer) and its neighbours, floor((k-1)/2) nearer
+    planes and the rest farther, the window moved inside [0, D). With tau >= 0, kept planes
+    whose A <= tau are dropped too."""
     A = select_scores_f32(alpha)
     D = A.shape[0]
     k = min(int(k), D)
-    order = np.argsort(-A, axis=0, kind="stable")       # ties keep ascending z
     mask = np.zeros(A.shape, dtype=bool)
-    np.put_along_axis(mask, order[:k], True, axis=0)
+    if rule == "topk":
+        order = np.argsort(-A, axis=0, kind="stable")       # ties keep ascending z
+        np.put_along_axis(mask, order[:k], True, axis=0)
+    elif rule == "mvs":
+        best = np.argmax(A, axis=0)                         # first (nearest) maximum
+        lo = np.clip(best - (k - 1) // 2, 0, D - k)
+        z = np.arange(D)[:, None, None]
+        mask = (z >= lo[None]) & (z < lo[None] + k)
+    else:
+        raise ValueError(rule)
     if tau >= 0:
         mask &= A > np.float32(tau)
     return mask
@@ -335,7 +347,7 @@ def target_pyramid(targets, levels):
 
 
 def refine(M0, targets, K_r, K, R, t, depths, iters, k, lr_rgb, lr_alpha, tau=-1.0,
-           bf16=False):
+           bf16=False, rule="topk"):
     """Coarse-to-fine HSGD with analytic descent. M0 is the initial MPI at the coarsest
     level, targets the full-resolution views. Per level: upsample (l > 0), then iters[l]
     times: select S on the current MPI, loss and dense gradient, sparse update on S.
@@ -356,7 +368,7 @@ def refine(M0, targets, K_r, K, R, t, depths, iters, k, lr_rgb, lr_alpha, tau=-1
         K_l = np.stack([level_intrinsics(K[i], W, H, Wl, Hl) for i in range(N)])
         G = view_to_ref_maps(Kr_l, K_l, R, t, depths)
         for _ in range(iters[l]):
-            mask = select_active(M[..., 3], k, tau)
+            mask = select_active(M[..., 3], k, tau, rule)
             loss, grad = loss_and_grad(M, G, pyr[l])
             mse = 2.0 * loss / (3.0 * Hl * Wl)          # sum of squares = 2 N L
             log.append(dict(level=l, loss=loss, active=int(mask.sum()),

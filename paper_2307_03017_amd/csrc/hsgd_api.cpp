@@ -26,18 +26,20 @@ hsgd_status hsgd_select_active(const hsgd_mpi* m, hsgd_select_params p, uint64_t
     if (!mask) return fail(HSGD_E_ARG, "%s: mask is NULL", fn);
     if (p.k < 1 || p.k > m->D) return fail(HSGD_E_ARG, "%s: k=%d outside [1, D=%d]", fn, p.k, m->D);
     if (std::isnan(p.tau)) return fail(HSGD_E_ARG, "%s: tau is NaN", fn);
+    if (p.rule != HSGD_SELECT_TOPK && p.rule != HSGD_SELECT_MVS)
+        return fail(HSGD_E_ARG, "%s: unknown selection rule %d", fn, p.rule);
     const bool any = ids || plane_off || n_active;
     if (any && !(ids && plane_off && n_active))
         return fail(HSGD_E_ARG, "%s: ids, plane_off and n_active must all be given or all NULL", fn);
     if (ids && (int64_t)cap < (int64_t)p.k * m->H * m->W)
         return fail(HSGD_E_CAPACITY, "%s: cap=%d < k*H*W=%lld", fn, cap,
                     (long long)p.k * m->H * m->W);
-    if (!ids) return hip_status(launch_select(*m, p.k, p.tau, mask, nullptr, nullptr, stream), fn);
+    if (!ids) return hip_status(launch_select(*m, p.k, p.tau, p.rule, mask, nullptr, nullptr, stream), fn);
     const ActiveLayout L = active_ws(m->D, m->H, m->W, cap, false);
     st = check_ws(ws, ws_bytes, L.bytes);
     if (st) return st;
     const ActiveSet as = active_at(ws, L, ids, n_active);
-    return hip_status(launch_select(*m, p.k, p.tau, mask, &as, plane_off, stream), fn);
+    return hip_status(launch_select(*m, p.k, p.tau, p.rule, mask, &as, plane_off, stream), fn);
 }
 
 hsgd_status hsgd_render(const hsgd_mpi* m, const hsgd_views* v, float* out_rgb,
@@ -146,6 +148,8 @@ hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
     if ((int64_t)sel.k * top.H * top.W >= ((int64_t)1 << 28))
         return fail(HSGD_E_SHAPE, "%s: k*H*W must stay below 2^28 gradient slots per view", fn);
     if (std::isnan(sel.tau)) return fail(HSGD_E_ARG, "%s: tau is NaN", fn);
+    if (sel.rule != HSGD_SELECT_TOPK && sel.rule != HSGD_SELECT_MVS)
+        return fail(HSGD_E_ARG, "%s: unknown selection rule %d", fn, sel.rule);
     if (!std::isfinite(lr_rgb) || !std::isfinite(lr_alpha))
         return fail(HSGD_E_ARG, "%s: learning rates must be finite", fn);
     const int N = views[0].N;
@@ -174,7 +178,7 @@ hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
         // a level's first selection comes out of the upsampling kernel that fills it
         const bool fused = l > 0 && iters[l] > 0;
         if (l > 0) {
-            int e = fused ? launch_upsample_select(levels[l - 1], levels[l], sel.k, sel.tau, mask, stream)
+            int e = fused ? launch_upsample_select(levels[l - 1], levels[l], sel.k, sel.tau, sel.rule, mask, stream)
                           : launch_upsample(levels[l - 1], levels[l], stream);
             if (e) return hip_status(e, fn);
         }
@@ -184,7 +188,7 @@ hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
         float4* slots = reinterpret_cast<float4*>(inner + G.slots_off);
         float* partials = reinterpret_cast<float*>(inner + G.partial_off);
         for (int it = 0; it < iters[l]; ++it, ++it_global) {
-            int e = (fused && it == 0) ? 0 : launch_select(levels[l], sel.k, sel.tau, mask, nullptr, nullptr, stream);
+            int e = (fused && it == 0) ? 0 : launch_select(levels[l], sel.k, sel.tau, sel.rule, mask, nullptr, nullptr, stream);
             if (e) return hip_status(e, fn);
             e = launch_grad_step(levels[l], v, mask, sel.k, nullptr, lr_rgb, lr_alpha, nullptr,
                                  loss_log ? loss_log + it_global : nullptr, slots, partials, stream);

@@ -172,6 +172,7 @@ void fill_table(hsgd_batch* b, BatchTable* t, std::vector<int>& order) {
         d.k = r.sel.k;
         d.kcap = r.sel.k;
         d.tau = r.sel.tau;
+        d.rule = r.sel.rule;
         d.lr_rgb = r.lr_rgb;
         d.lr_alpha = r.lr_alpha;
         d.ntx = (int)ceil_div(m.W + 1, kShiftOX);
@@ -328,6 +329,8 @@ hsgd_status hsgd_batch_admit(hsgd_batch* b, const hsgd_request* r, int64_t* tick
     if (r->sel.k < 1 || r->sel.k > top.D || r->sel.k > c.max_k)
         return fail(HSGD_E_ARG, "%s: k=%d outside [1, min(D, max_k)]", fn, r->sel.k);
     if (std::isnan(r->sel.tau)) return fail(HSGD_E_ARG, "%s: tau is NaN", fn);
+    if (r->sel.rule != HSGD_SELECT_TOPK && r->sel.rule != HSGD_SELECT_MVS)
+        return fail(HSGD_E_ARG, "%s: unknown selection rule %d", fn, r->sel.rule);
     if (!std::isfinite(r->lr_rgb) || !std::isfinite(r->lr_alpha))
         return fail(HSGD_E_ARG, "%s: learning rates must be finite", fn);
 

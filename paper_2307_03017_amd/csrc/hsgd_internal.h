@@ -106,7 +106,7 @@ class ProfScope {
 
 // ---- kernel launchers (hsgd_kernels.hip); return hipSuccess or the launch error ----
 // select: mask (nullable) and, when as != NULL, the active set (plane_off nullable).
-int launch_select(const hsgd_mpi& m, int k, float tau, uint64_t* mask, const ActiveSet* as,
+int launch_select(const hsgd_mpi& m, int k, float tau, int rule, uint64_t* mask, const ActiveSet* as,
                   int32_t* plane_off, hipStream_t s);
 int launch_render(const hsgd_mpi& m, const hsgd_views& v, float* out_rgb, float* out_loss,
                   void* ws, hipStream_t s);
@@ -116,7 +116,7 @@ int launch_grad_step(const hsgd_mpi& m, const hsgd_views& v, const uint64_t* mas
                      float4* slots, float* partials, hipStream_t s);
 int launch_upsample(const hsgd_mpi& coarse, const hsgd_mpi& fine, hipStream_t s);
 // upsampling into `fine` fused with the selection on the stored result (mask [H][W])
-int launch_upsample_select(const hsgd_mpi& coarse, const hsgd_mpi& fine, int k, float tau, uint64_t* mask,
+int launch_upsample_select(const hsgd_mpi& coarse, const hsgd_mpi& fine, int k, float tau, int rule, uint64_t* mask,
                            hipStream_t s);
 int launch_downsample(const float* img, int N, int H, int W, float* out, hipStream_t s);
 int launch_convert(const void* src, int sdt, void* dst, int ddt, size_t n, hipStream_t s);
@@ -151,7 +151,8 @@ struct BatchSlot {
     int D, H, W, N;
     int uh, uw;                       // upsampling source shape
     int k, kcap, ntx, nty;
-    float tau, lr_rgb, lr_alpha, pad_;
+    float tau, lr_rgb, lr_alpha;
+    int rule;                         // selection rule (HSGD_SELECT_*)
 };
 
 struct BatchTable {

@@ -207,15 +207,28 @@ __device__ __forceinline__ float score_step(float a, float& T) {
     return (s == s) ? s : -INFINITY;
 }
 
-// The plane mask of the k largest scores A[0..D) (equal scores: the nearer plane), then the
-// optional threshold.
+// The plane mask of the selection rule on the scores A[0..D), then the optional threshold.
+// Top-k: the k largest scores (equal scores: the nearer plane). MVS window: the largest
+// score (equal: the nearer plane) with (k-1)/2 planes before it (rounded down) and the
+// rest after, moved inside [0, D).
 template <int MAXD>
-__device__ __forceinline__ uint64_t topk_bits(const float (&A)[MAXD], int D, int k, float tau) {
+__device__ __forceinline__ uint64_t topk_bits(const float (&A)[MAXD], int D, int k, float tau, int rule) {
     const uint64_t full = D == 64 ? ~0ull : ((1ull << D) - 1);
     const int kk = min(k, D);
     uint64_t sel = 0;
     if (kk == D) {
         sel = full;
+    } else if (rule == HSGD_SELECT_MVS) {
+        int best = 0;
+        float bestA = A[0];
+#pragma unroll
+        for (int z = 1; z < MAXD; ++z)
+            if (z < D && A[z] > bestA) {
+                best = z;
+                bestA = A[z];
+            }
+        const int lo = min(max(best - (kk - 1) / 2, 0), D - kk);
+        sel = (kk == 64 ? ~0ull : ((1ull << kk) - 1)) << lo;
     } else if (2 * kk <= D) {
         // kk passes: the best remaining score, the nearer plane on equal scores
         for (int j = 0; j < kk; ++j) {
@@ -257,7 +270,7 @@ __device__ __forceinline__ uint64_t topk_bits(const float (&A)[MAXD], int D, int
 // need no guard): one memory latency per pixel rather than one per plane.
 template <int DT, int MAXD>
 __device__ __forceinline__ uint64_t select_bits(const void* __restrict__ mpi, int D, int HW, int p,
-                                                int k, float tau) {
+                                                int k, float tau, int rule) {
     float a[MAXD];
 #pragma unroll
     for (int z = 0; z < MAXD; ++z) a[z] = Vox<DT>::alpha(mpi, min(z, D - 1) * HW + p);
@@ -266,7 +279,7 @@ __device__ __forceinline__ uint64_t select_bits(const void* __restrict__ mpi, in
 #pragma unroll
     for (int z = 0; z < MAXD; ++z)
         if (z < D) A[z] = score_step(a[z], T);
-    return topk_bits<MAXD>(A, D, k, tau);
+    return topk_bits<MAXD>(A, D, k, tau, rule);
 }
 
 // The transposed view of a 64-pixel block's masks: for every plane the wave ballot (bit
@@ -284,13 +297,13 @@ __device__ __forceinline__ void emit_ballots(uint64_t sel, int D, int64_t wblk, 
 
 template <int DT, int MAXD>
 __global__ __launch_bounds__(256) void k_select(const void* __restrict__ mpi, int D, int HW, int k,
-                                                float tau, uint64_t* __restrict__ mask,
+                                                float tau, int rule, uint64_t* __restrict__ mask,
                                                 uint64_t* __restrict__ bal, int* __restrict__ cnt,
                                                 int64_t nblk) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t sel = 0;
     if (p < HW) {
-        sel = select_bits<DT, MAXD>(mpi, D, HW, p, k, tau);
+        sel = select_bits<DT, MAXD>(mpi, D, HW, p, k, tau, rule);
         if (mask) mask[p] = sel;
     }
     if (bal) emit_ballots(sel, D, (int64_t)p >> 6, nblk, bal, cnt);
@@ -1190,7 +1203,7 @@ __global__ __launch_bounds__(256) void k_upsample(const void* __restrict__ src, 
 // mask equals what k_select computes from the stored level.
 template <int DT, int MAXD>
 __global__ __launch_bounds__(256) void k_upsample_select(const void* __restrict__ src, int D, int h, int w,
-                                                         void* __restrict__ dst, int k, float tau,
+                                                         void* __restrict__ dst, int k, float tau, int rule,
                                                          uint64_t* __restrict__ mask) {
     const int W2 = 2 * w, H2 = 2 * h;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1209,7 +1222,7 @@ __global__ __launch_bounds__(256) void k_upsample_select(const void* __restrict_
         for (int j = 0; j < kG; ++j)
             if (z0 + j < D) A[z0 + j] = score_step(upsample_store<DT>(t[j], dst, W2 * H2, z0 + j, i).w, T);
     }
-    mask[i] = topk_bits<MAXD>(A, D, k, tau);
+    mask[i] = topk_bits<MAXD>(A, D, k, tau, rule);
 }
 
 // Output pixel i of view n of the 2x2 box mean of [N][H][W][3] images.
@@ -1286,7 +1299,7 @@ __global__ __launch_bounds__(256) void k_batch_select(const BatchTable* __restri
         const BatchSlot& b = t->slot[sl];
         const int p = (g - t->pre[BK_SELECT][sl]) * 256 + threadIdx.x;
         const int HW = b.H * b.W;
-        if (p < HW) b.mask[p] = select_bits<DT, MAXD>(b.mpi, b.D, HW, p, b.k, b.tau);
+        if (p < HW) b.mask[p] = select_bits<DT, MAXD>(b.mpi, b.D, HW, p, b.k, b.tau, b.rule);
     }
 }
 
@@ -1358,14 +1371,14 @@ static int launch_scan_compact(const ActiveSet& as, int D, int HW, int* plane_of
     return (int)hipGetLastError();
 }
 
-int launch_select(const hsgd_mpi& m, int k, float tau, uint64_t* mask, const ActiveSet* as,
+int launch_select(const hsgd_mpi& m, int k, float tau, int rule, uint64_t* mask, const ActiveSet* as,
                   int32_t* plane_off, hipStream_t s) {
     const int HW = m.H * m.W;
     const dim3 grid((unsigned)ceil_div(HW, 256));
     {
         ProfScope ps(HSGD_K_SELECT, s);
         HSGD_DISPATCH_T(m.dtype, HSGD_DISPATCH_D(m.D, hipLaunchKernelGGL((k_select<DT, MD>), grid, dim3(256), 0, s,
-                                                                        m.rgba, m.D, HW, k, tau, mask,
+                                                                        m.rgba, m.D, HW, k, tau, rule, mask,
                                                                         as ? as->bal : nullptr,
                                                                         as ? as->off : nullptr,
                                                                         as ? as->nblk : (int64_t)0)));
@@ -1475,11 +1488,13 @@ int launch_upsample(const hsgd_mpi& c, const hsgd_mpi& f, hipStream_t s) {
     return (int)hipGetLastError();
 }
 
-int launch_upsample_select(const hsgd_mpi& c, const hsgd_mpi& f, int k, float tau, uint64_t* mask, hipStream_t s) {
+int launch_upsample_select(const hsgd_mpi& c, const hsgd_mpi& f, int k, float tau, int rule, uint64_t* mask,
+                           hipStream_t s) {
     const dim3 grid((unsigned)ceil_div((int64_t)f.H * f.W, 256));
     ProfScope ps(HSGD_K_UPSAMPLE, s);
     HSGD_DISPATCH_T(c.dtype, HSGD_DISPATCH_D(c.D, hipLaunchKernelGGL((k_upsample_select<DT, MD>), grid, dim3(256), 0, s,
-                                                                    c.rgba, c.D, c.H, c.W, f.rgba, k, tau, mask)));
+                                                                    c.rgba, c.D, c.H, c.W, f.rgba, k, tau, rule,
+                                                                    mask)));
     return (int)hipGetLastError();
 }
 

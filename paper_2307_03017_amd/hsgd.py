@@ -48,8 +48,19 @@ class Views(ctypes.Structure):
 HSGD_VIEWS_SHIFT_ONLY = 1
 
 
+SELECT_TOPK, SELECT_MVS = 0, 1
+_RULES = {"topk": SELECT_TOPK, "mvs": SELECT_MVS, SELECT_TOPK: SELECT_TOPK, SELECT_MVS: SELECT_MVS}
+
+
 class SelectParams(ctypes.Structure):
-    _fields_ = [("k", ctypes.c_int32), ("tau", ctypes.c_float)]
+    _fields_ = [("k", ctypes.c_int32), ("tau", ctypes.c_float), ("rule", ctypes.c_int32)]
+
+
+def select_params(k: int, tau: float = -1.0, rule="topk") -> SelectParams:
+    """rule: "topk" (the paper's rule) or "mvs" (the MVS-sampling window)."""
+    if rule not in _RULES:
+        raise ValueError(f"unknown selection rule {rule!r}")
+    return SelectParams(int(k), float(tau), _RULES[rule])
 
 
 assert ctypes.sizeof(Warp) == 64
@@ -272,7 +283,7 @@ def level_warps(K_ref, K, R, t, depths, W: int, H: int, Wl: int, Hl: int, device
 # device calls
 # ---------------------------------------------------------------------------------------
 def hsgd_select_active(rgba: torch.Tensor, k: int, tau: float = -1.0, with_ids: bool = True,
-                       mask: torch.Tensor | None = None, stream=None):
+                       mask: torch.Tensor | None = None, stream=None, rule="topk"):
     """Returns mask (int64 [H][W], bit z = voxel (z, p) selected) and, if with_ids,
     (ids int32 [k*H*W] capacity, plane_off int32 [D+1], n_active int32 [1])."""
     m = mpi_desc(rgba)
@@ -287,7 +298,7 @@ def hsgd_select_active(rgba: torch.Tensor, k: int, tau: float = -1.0, with_ids: 
         plane_off = torch.empty(m.D + 1, dtype=torch.int32, device=dev)
         n_active = torch.empty(1, dtype=torch.int32, device=dev)
         ws = workspace(OP_SELECT, m.D, m.H, m.W, 1, k, device=dev)
-    _check(lib().hsgd_select_active(ctypes.byref(m), SelectParams(k, tau), _ptr(mask), _ptr(ids), cap,
+    _check(lib().hsgd_select_active(ctypes.byref(m), select_params(k, tau, rule), _ptr(mask), _ptr(ids), cap,
                                     _ptr(plane_off), _ptr(n_active), _ptr(ws),
                                     0 if ws is None else ws.numel(), _stream(stream)))
     if with_ids:
@@ -405,8 +416,9 @@ class RefinePlan:
 
     def __init__(self, K_ref, K, R, t, depths, W: int, H: int, iters: Sequence[int], k: int,
                  tau: float = -1.0, lr_rgb: float = 1.0, lr_alpha: float = 1.0,
-                 dtype: torch.dtype = torch.float32, device="cuda"):
+                 dtype: torch.dtype = torch.float32, device="cuda", rule="topk"):
         L = len(iters)
+        self.sel = select_params(k, tau, rule)
         self.L, self.iters, self.k, self.tau = L, tuple(int(i) for i in iters), int(k), float(tau)
         self.lr_rgb, self.lr_alpha = float(lr_rgb), float(lr_alpha)
         self.N = int(np.asarray(K).reshape(-1, 3, 3).shape[0])
@@ -430,18 +442,18 @@ class RefinePlan:
     def run(self, images: torch.Tensor, descriptors=None, stream=None):
         """Refine levels[0] (the initial MPI, already written by the caller) up to levels[-1]."""
         mpis, vs = descriptors or self.descriptors(images)
-        _check(lib().hsgd_refine(mpis, vs, self.L, self._iters, SelectParams(self.k, self.tau),
+        _check(lib().hsgd_refine(mpis, vs, self.L, self._iters, self.sel,
                                  self.lr_rgb, self.lr_alpha, _ptr(self.loss_log), _ptr(self.ws),
                                  self.ws.numel(), _stream(stream)))
         return self.levels[-1]
 
 
 def hsgd_refine(init: torch.Tensor, images: torch.Tensor, K_ref, K, R, t, depths, iters, k,
-                tau: float = -1.0, lr_rgb: float = 1.0, lr_alpha: float = 1.0, stream=None):
+                tau: float = -1.0, lr_rgb: float = 1.0, lr_alpha: float = 1.0, stream=None, rule="topk"):
     """One-shot refinement: returns (final MPI, per-iteration losses)."""
     N, H, W, _ = images.shape
     plan = RefinePlan(K_ref, K, R, t, depths, W, H, iters, k, tau, lr_rgb, lr_alpha,
-                      dtype=init.dtype, device=init.device)
+                      dtype=init.dtype, device=init.device, rule=rule)
     plan.levels[0].copy_(init)
     plan.run(images, stream=stream)
     return plan.levels[-1], plan.loss_log[:sum(plan.iters)]
@@ -458,7 +470,7 @@ class ServingStream:
 
     def __init__(self, stream_id: int, K_ref, K, R, t, depths, W: int, H: int, iters: Sequence[int], k: int,
                  dtype: torch.dtype = torch.bfloat16, tau: float = -1.0, lr_rgb: float = 1.0,
-                 lr_alpha: float = 1.0, device="cuda"):
+                 lr_alpha: float = 1.0, device="cuda", rule="topk"):
         L = len(iters)
         if L > MAX_BATCH_LEVELS:
             raise ValueError(f"at most {MAX_BATCH_LEVELS} levels")
@@ -478,7 +490,7 @@ class ServingStream:
             req.levels[l] = mpi_desc(self.levels[l])
             req.views[l] = views_desc(self.warps[l], self.N, h, w, self.images[l])
             req.iters[l] = self.iters[l]
-        req.sel = SelectParams(self.k, float(tau))
+        req.sel = select_params(self.k, tau, rule)
         req.lr_rgb, req.lr_alpha = float(lr_rgb), float(lr_alpha)
         req.loss_log = _ptr(self.loss_log)
         self.request = req

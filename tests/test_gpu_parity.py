@@ -118,8 +118,9 @@ SELECT_CASES = [
 ]
 
 
+@pytest.mark.parametrize("rule", ["topk", "mvs"])
 @pytest.mark.parametrize("case", SELECT_CASES, ids=lambda c: f"seed{c[0]}_D{c[1]}_k{c[4]}")
-def test_select_bit_exact(case):
+def test_select_bit_exact(case, rule):
     seed, D, W, H, k, tau, quant, dtype = case
     rng = np.random.default_rng(seed)
     M = rng.uniform(size=(D, H, W, 4))
@@ -131,9 +132,9 @@ def test_select_bit_exact(case):
     M = f32(M)
     Md = to_dev(M, dtype)
     alpha = M[..., 3] if dtype == torch.float32 else bf16_vals(M)[..., 3]
-    ref = O.select_active(alpha, k, tau)
+    ref = O.select_active(alpha, k, tau, rule)
     ref_ids, ref_off = O.select_ids(ref)
-    mask, ids, off, n = hsgd.hsgd_select_active(Md, k, tau)
+    mask, ids, off, n = hsgd.hsgd_select_active(Md, k, tau, rule=rule)
     torch.cuda.synchronize()
     got = mask_bits(mask.cpu().numpy(), D)
     assert np.array_equal(got, ref)
@@ -292,15 +293,17 @@ def test_refine_tiny_scene_teacher_forced():
             M = nxt
 
 
-@pytest.mark.parametrize("name", ["c1", "c2"])
-def test_refine_end_to_end(name):
-    """hsgd_refine in one call vs the oracle refine: per-iteration losses and final PSNR.
-    (No teacher forcing: FP32 drift may flip a near-tie selection, so compare outcomes.)"""
+@pytest.mark.parametrize("name,rule", [("c1", "topk"), ("c2", "topk"), ("c1", "mvs"), ("c2", "mvs")])
+def test_refine_end_to_end(name, rule):
+    """hsgd_refine in one call vs the oracle refine: per-iteration losses and final PSNR,
+    with either selection rule. (No teacher forcing: FP32 drift may flip a near-tie
+    selection, so compare outcomes.)"""
     sc, init, targets = scene_inputs(name)
     M_ref, log = O.refine(init, targets, sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(),
-                          sc.depths, sc.iters, sc.k, 1.0, 1.0)
+                          sc.depths, sc.iters, sc.k, 1.0, 1.0, rule=rule)
     final, losses = hsgd.hsgd_refine(to_dev(init), to_dev(targets), sc.K_ref(), sc.K_views(), sc.R_views(),
-                                     sc.t_views(), sc.depths, sc.iters, sc.k, lr_rgb=1.0, lr_alpha=1.0)
+                                     sc.t_views(), sc.depths, sc.iters, sc.k, lr_rgb=1.0, lr_alpha=1.0,
+                                     rule=rule)
     torch.cuda.synchronize()
     ref_losses = np.array([e["loss"] for e in log])
     np.testing.assert_allclose(losses.cpu().numpy(), ref_losses, rtol=1e-4)

@@ -145,3 +145,25 @@ def test_poisson_loop_latency_and_results(mix):
     for t, (req, res) in list(snaps.items())[:10]:
         ref, _ = alone(mix[req.scene], req.variant, torch.bfloat16)
         assert torch.equal(res, ref)
+
+
+def test_mvs_rule_request_equals_refine(mix):
+    """A request with the MVS-sampling selection through the batch equals hsgd_refine with
+    that rule alone (bitwise), and differs from the top-k request."""
+    si = mix[2]
+    sc = si.sc
+    st = serving.new_stream(0, si)
+    st_m = hsgd.ServingStream(1, sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths, sc.W, sc.H,
+                              sc.iters, 5, rule="mvs")
+    st_m.images[-1].copy_(si.targets)
+    b = hsgd.Batch(2, sc.D, sc.N, sc.H, sc.W, 5)
+    for s_ in (st, st_m):
+        s_.levels[0].copy_(si.inits[0])
+        assert b.admit(s_) is not None
+    while b.step()[0]:
+        pass
+    torch.cuda.synchronize()
+    ref, _ = hsgd.hsgd_refine(si.inits[0], si.targets, sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(),
+                              sc.depths, sc.iters, 5, rule="mvs")
+    assert torch.equal(st_m.result, ref)
+    assert not torch.equal(st_m.result, st.result)

@@ -298,6 +298,45 @@ def test_topk_against_brute_force(D, k):
     assert np.all(mask.sum(axis=0) == min(k, D))
 
 
+def _brute_mvs(A, k):
+    """MVS-sampling by enumeration: among all windows of k consecutive planes inside [0, D)
+    that contain the first maximum of A, the one whose start is nearest to that maximum
+    minus floor((k-1)/2)."""
+    D = A.shape[0]
+    mask = np.zeros(A.shape, bool)
+    for idx in itertools.product(*[range(s) for s in A.shape[1:]]):
+        col = A[(slice(None),) + idx]
+        best = max(range(D), key=lambda z: (col[z], -z))
+        starts = [s for s in range(D - k + 1) if s <= best < s + k]
+        want = best - (k - 1) // 2
+        lo = min(starts, key=lambda s: abs(s - want))
+        mask[(slice(lo, lo + k),) + idx] = True
+    return mask
+
+
+@pytest.mark.parametrize("D,k", [(6, 1), (6, 3), (8, 3), (8, 4), (9, 5), (5, 5)])
+def test_mvs_window_against_brute_force(D, k):
+    rng = RNG(60 + D + k)
+    a = rng.integers(0, 5, size=(D, 5, 6)).astype(np.float32) / 4      # exact ties in A
+    A = O.select_scores_f32(a)
+    mask = O.select_active(a, k, rule="mvs")
+    np.testing.assert_array_equal(mask, _brute_mvs(A, min(k, D)))
+    assert np.all(mask.sum(axis=0) == min(k, D))
+    # the window is contiguous and holds the top-1 plane of the top-k rule
+    assert np.all(mask >= O.select_active(a, 1))
+
+
+def test_mvs_window_of_one_opaque_plane():
+    # an opaque plane at z0 (transparent elsewhere) has A = one-hot(z0): the window centres
+    # on it, moved inside the stack at the ends
+    D, k = 8, 5
+    for z0, lo in [(0, 0), (1, 0), (2, 0), (4, 2), (6, 3), (7, 3)]:
+        a = np.zeros((D, 1, 1), np.float32)
+        a[z0] = 1.0
+        m = O.select_active(a, k, rule="mvs")[:, 0, 0]
+        assert list(np.flatnonzero(m)) == list(range(lo, lo + k)), (z0, np.flatnonzero(m))
+
+
 def test_select_scores_follow_eq_gradient():
     # A_z = a_z prod_{j<z}(1 - a_j), the paper's alpha gradient on the reference view
     rng = RNG(31)
