@@ -199,6 +199,10 @@ hsgd_status hsgd_render(const hsgd_mpi* m, const hsgd_views* v, float* out_rgb,
  *  kcap  most bits set in any mask word (the k given to hsgd_select_active; D when
  *        mask == NULL). Planes of a pixel beyond its first kcap set bits are treated as
  *        not selected.
+ *  lambda_s  weight of the sparsity prior (Sec. 3.4, L_s = mean over the level's voxels of
+ *        log(1.5 - |0.5 - alpha|), the prior phi of Eq. 4); 0 = none. When non-zero, its
+ *        alpha gradient lambda_s sign(0.5 - alpha) / ((1.5 - |0.5 - alpha|) D H W) (0 at
+ *        alpha = 0.5) is added to g on S. out_loss stays the data term.
  * Then, if lr_rgb or lr_alpha is non-zero, M[S] <- clamp(M[S] - (lr_rgb x3, lr_alpha) g,
  * 0, 1) in place (BF16 storage: round to nearest even on store); voxels outside S are
  * never written.
@@ -207,8 +211,8 @@ hsgd_status hsgd_render(const hsgd_mpi* m, const hsgd_views* v, float* out_rgb,
  */
 hsgd_status hsgd_grad_step(hsgd_mpi* m, const hsgd_views* v, const uint64_t* mask,
                            int32_t kcap, const float* dimg, float lr_rgb, float lr_alpha,
-                           float* grad_out, float* out_loss, void* ws, size_t ws_bytes,
-                           hipStream_t stream);
+                           float lambda_s, float* grad_out, float* out_loss, void* ws,
+                           size_t ws_bytes, hipStream_t stream);
 
 /*
  * hsgd_upsample2x -- MPI level transition (Sec. 3.3: refine the upsampled MPI).
@@ -236,12 +240,13 @@ hsgd_status hsgd_downsample2x(const float* images, int32_t N, int32_t H, int32_t
  *          they are computed as 2x2 box means of the next finer level into the workspace.
  *  iters   host [L] iterations per level (>= 0).
  *  sel     sparsification rule (k, tau, rule) used at every iteration.
+ *  lr_rgb, lr_alpha, lambda_s  as in hsgd_grad_step, at every iteration.
  *  loss_log device [sum(iters)] FP32 or NULL: loss of each iteration before its update.
  */
 hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
                         const int32_t* iters, hsgd_select_params sel, float lr_rgb,
-                        float lr_alpha, float* loss_log, void* ws, size_t ws_bytes,
-                        hipStream_t stream);
+                        float lr_alpha, float lambda_s, float* loss_log, void* ws,
+                        size_t ws_bytes, hipStream_t stream);
 
 /*
  * hsgd_convert -- storage conversion of n floats: FP32 -> BF16 (round to nearest even),
@@ -292,6 +297,7 @@ typedef struct {
     int32_t iters[HSGD_MAX_BATCH_LEVELS];     /* >= 1, except level 0 which may be 0       */
     hsgd_select_params sel;
     float lr_rgb, lr_alpha;
+    float lambda_s;                           /* sparsity prior weight, as in grad_step    */
     float* loss_log;                          /* device [sum(iters)] FP32 or NULL          */
 } hsgd_request;
 

@@ -295,6 +295,20 @@ def bf16_round(x):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+def sparsity_loss(alpha):
+    """L_s of Sec. 3.4: the mean over the level's voxels of log(1.5 - |0.5 - alpha|)."""
+    a = np.asarray(alpha, float)
+    return float(np.mean(np.log(1.5 - np.abs(0.5 - a))))
+
+
+def sparsity_grad(alpha):
+    """dL_s/dalpha per voxel: sign(0.5 - alpha) / (1.5 - |0.5 - alpha|) / (D H W), taking the
+    subgradient 0 at alpha = 0.5 (descent moves alpha towards 0 below 0.5, towards 1 above)."""
+    a = np.asarray(alpha, float)
+    d = 0.5 - a
+    return np.sign(d) / (1.5 - np.abs(d)) / a.size
+
+
 def apply_update(M, grad, mask, lr_rgb, lr_alpha, bf16=False):
     """M <- clip(M - lambda * grad, 0, 1) on the active voxels, unchanged elsewhere."""
     lam = np.array([lr_rgb, lr_rgb, lr_rgb, lr_alpha])
@@ -347,7 +361,7 @@ def target_pyramid(targets, levels):
 
 
 def refine(M0, targets, K_r, K, R, t, depths, iters, k, lr_rgb, lr_alpha, tau=-1.0,
-           bf16=False, rule="topk"):
+           bf16=False, rule="topk", lambda_s=0.0):
     """Coarse-to-fine HSGD with analytic descent. M0 is the initial MPI at the coarsest
     level, targets the full-resolution views. Per level: upsample (l > 0), then iters[l]
     times: select S on the current MPI, loss and dense gradient, sparse update on S.
@@ -370,6 +384,8 @@ def refine(M0, targets, K_r, K, R, t, depths, iters, k, lr_rgb, lr_alpha, tau=-1
         for _ in range(iters[l]):
             mask = select_active(M[..., 3], k, tau, rule)
             loss, grad = loss_and_grad(M, G, pyr[l])
+            if lambda_s:
+                grad[..., 3] += lambda_s * sparsity_grad(M[..., 3])     # the prior phi of Eq. 4
             mse = 2.0 * loss / (3.0 * Hl * Wl)          # sum of squares = 2 N L
             log.append(dict(level=l, loss=loss, active=int(mask.sum()),
                             psnr=float("inf") if mse == 0 else 10.0 * np.log10(1.0 / mse)))

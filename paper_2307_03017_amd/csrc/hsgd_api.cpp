@@ -60,8 +60,8 @@ hsgd_status hsgd_render(const hsgd_mpi* m, const hsgd_views* v, float* out_rgb,
 
 hsgd_status hsgd_grad_step(hsgd_mpi* m, const hsgd_views* v, const uint64_t* mask,
                            int32_t kcap, const float* dimg, float lr_rgb, float lr_alpha,
-                           float* grad_out, float* out_loss, void* ws, size_t ws_bytes,
-                           hipStream_t stream) {
+                           float lambda_s, float* grad_out, float* out_loss, void* ws,
+                           size_t ws_bytes, hipStream_t stream) {
     clear_error();
     const char* fn = "hsgd_grad_step";
     hsgd_status st = check_mpi(m, fn);
@@ -72,15 +72,15 @@ hsgd_status hsgd_grad_step(hsgd_mpi* m, const hsgd_views* v, const uint64_t* mas
     if (kcap < 1 || kcap > m->D) return fail(HSGD_E_ARG, "%s: kcap=%d outside [1, D=%d]", fn, kcap, m->D);
     if ((int64_t)kcap * m->H * m->W >= ((int64_t)1 << 28))
         return fail(HSGD_E_SHAPE, "%s: kcap*H*W must stay below 2^28 gradient slots per view", fn);
-    if (!std::isfinite(lr_rgb) || !std::isfinite(lr_alpha))
-        return fail(HSGD_E_ARG, "%s: learning rates must be finite", fn);
+    if (!std::isfinite(lr_rgb) || !std::isfinite(lr_alpha) || !std::isfinite(lambda_s))
+        return fail(HSGD_E_ARG, "%s: learning rates and lambda_s must be finite", fn);
     const GradWs L = grad_ws(m->D, m->H, m->W, v->N, kcap);
     st = check_ws(ws, ws_bytes, L.bytes);
     if (st) return st;
     float4* slots = reinterpret_cast<float4*>((char*)ws + L.slots_off);
     float* partials = reinterpret_cast<float*>((char*)ws + L.partial_off);
-    return hip_status(launch_grad_step(*m, *v, mask, kcap, dimg, lr_rgb, lr_alpha, grad_out, out_loss, slots,
-                                       partials, stream), fn);
+    return hip_status(launch_grad_step(*m, *v, mask, kcap, dimg, lr_rgb, lr_alpha, lambda_s, grad_out, out_loss,
+                                       slots, partials, stream), fn);
 }
 
 hsgd_status hsgd_upsample2x(const hsgd_mpi* coarse, hsgd_mpi* fine, hipStream_t stream) {
@@ -120,8 +120,8 @@ hsgd_status hsgd_convert(const void* src, int32_t src_dtype, void* dst, int32_t 
 
 hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
                         const int32_t* iters, hsgd_select_params sel, float lr_rgb,
-                        float lr_alpha, float* loss_log, void* ws, size_t ws_bytes,
-                        hipStream_t stream) {
+                        float lr_alpha, float lambda_s, float* loss_log, void* ws,
+                        size_t ws_bytes, hipStream_t stream) {
     clear_error();
     const char* fn = "hsgd_refine";
     if (!levels || !views || !iters) return fail(HSGD_E_ARG, "%s: NULL pointer", fn);
@@ -150,8 +150,8 @@ hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
     if (std::isnan(sel.tau)) return fail(HSGD_E_ARG, "%s: tau is NaN", fn);
     if (sel.rule != HSGD_SELECT_TOPK && sel.rule != HSGD_SELECT_MVS)
         return fail(HSGD_E_ARG, "%s: unknown selection rule %d", fn, sel.rule);
-    if (!std::isfinite(lr_rgb) || !std::isfinite(lr_alpha))
-        return fail(HSGD_E_ARG, "%s: learning rates must be finite", fn);
+    if (!std::isfinite(lr_rgb) || !std::isfinite(lr_alpha) || !std::isfinite(lambda_s))
+        return fail(HSGD_E_ARG, "%s: learning rates and lambda_s must be finite", fn);
     const int N = views[0].N;
     const RefineWs R = refine_ws(top.D, top.H, top.W, N, sel.k, L);
     st = check_ws(ws, ws_bytes, R.bytes);
@@ -190,7 +190,7 @@ hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
         for (int it = 0; it < iters[l]; ++it, ++it_global) {
             int e = (fused && it == 0) ? 0 : launch_select(levels[l], sel.k, sel.tau, sel.rule, mask, nullptr, nullptr, stream);
             if (e) return hip_status(e, fn);
-            e = launch_grad_step(levels[l], v, mask, sel.k, nullptr, lr_rgb, lr_alpha, nullptr,
+            e = launch_grad_step(levels[l], v, mask, sel.k, nullptr, lr_rgb, lr_alpha, lambda_s, nullptr,
                                  loss_log ? loss_log + it_global : nullptr, slots, partials, stream);
             if (e) return hip_status(e, fn);
         }

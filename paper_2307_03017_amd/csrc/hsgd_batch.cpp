@@ -173,6 +173,7 @@ void fill_table(hsgd_batch* b, BatchTable* t, std::vector<int>& order) {
         d.kcap = r.sel.k;
         d.tau = r.sel.tau;
         d.rule = r.sel.rule;
+        d.prior = (float)((double)r.lambda_s / ((double)m.D * m.H * m.W));
         d.lr_rgb = r.lr_rgb;
         d.lr_alpha = r.lr_alpha;
         d.ntx = (int)ceil_div(m.W + 1, kShiftOX);
@@ -331,8 +332,8 @@ hsgd_status hsgd_batch_admit(hsgd_batch* b, const hsgd_request* r, int64_t* tick
     if (std::isnan(r->sel.tau)) return fail(HSGD_E_ARG, "%s: tau is NaN", fn);
     if (r->sel.rule != HSGD_SELECT_TOPK && r->sel.rule != HSGD_SELECT_MVS)
         return fail(HSGD_E_ARG, "%s: unknown selection rule %d", fn, r->sel.rule);
-    if (!std::isfinite(r->lr_rgb) || !std::isfinite(r->lr_alpha))
-        return fail(HSGD_E_ARG, "%s: learning rates must be finite", fn);
+    if (!std::isfinite(r->lr_rgb) || !std::isfinite(r->lr_alpha) || !std::isfinite(r->lambda_s))
+        return fail(HSGD_E_ARG, "%s: learning rates and lambda_s must be finite", fn);
 
     auto it = b->streams.find(r->stream_id);
     if (it != b->streams.end() && it->second.in_flight)

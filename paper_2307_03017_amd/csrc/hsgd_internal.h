@@ -112,8 +112,8 @@ int launch_render(const hsgd_mpi& m, const hsgd_views& v, float* out_rgb, float*
                   void* ws, hipStream_t s);
 // mask NULL: every voxel selected (kcap = D); otherwise the first kcap planes of each pixel.
 int launch_grad_step(const hsgd_mpi& m, const hsgd_views& v, const uint64_t* mask, int kcap,
-                     const float* dimg, float lr_rgb, float lr_alpha, float* grad_out, float* out_loss,
-                     float4* slots, float* partials, hipStream_t s);
+                     const float* dimg, float lr_rgb, float lr_alpha, float lambda_s, float* grad_out,
+                     float* out_loss, float4* slots, float* partials, hipStream_t s);
 int launch_upsample(const hsgd_mpi& coarse, const hsgd_mpi& fine, hipStream_t s);
 // upsampling into `fine` fused with the selection on the stored result (mask [H][W])
 int launch_upsample_select(const hsgd_mpi& coarse, const hsgd_mpi& fine, int k, float tau, int rule, uint64_t* mask,
@@ -153,6 +153,8 @@ struct BatchSlot {
     int k, kcap, ntx, nty;
     float tau, lr_rgb, lr_alpha;
     int rule;                         // selection rule (HSGD_SELECT_*)
+    float prior;                      // sparsity prior weight over D H W of the level
+    int pad_[3];
 };
 
 struct BatchTable {

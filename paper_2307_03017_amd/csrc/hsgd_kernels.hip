@@ -1046,8 +1046,8 @@ __device__ __forceinline__ void update_block(void* __restrict__ mpi, int D, int 
                                              int cover_h, float lr_rgb, float lr_a, int do_update,
                                              float4* __restrict__ grad_out,
                                              const float* __restrict__ partials, int64_t nparts,
-                                             double loss_scale, float* __restrict__ out_loss, int blk,
-                                             int2* __restrict__ s_off) {
+                                             double loss_scale, float* __restrict__ out_loss, float prior,
+                                             int blk, int2* __restrict__ s_off) {
     if (SHIFT) {
         for (int i = threadIdx.x; i < nslices * D; i += blockDim.x) s_off[i] = make_int2(warps[i].ix, warps[i].iy);
         __syncthreads();
@@ -1109,8 +1109,14 @@ __device__ __forceinline__ void update_block(void* __restrict__ mpi, int D, int 
         const int z = __ffsll((unsigned long long)b) - 1;
         b &= b - 1;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (do_update) v = Vox<DT>::load(mpi, z * HW + p);     // in flight with the slices
-        const float4 g = grad_of(z, r++);
+        if (do_update || prior != 0.0f) v = Vox<DT>::load(mpi, z * HW + p);   // in flight with the slices
+        float4 g = grad_of(z, r++);
+        if (prior != 0.0f) {
+            // sparsity prior: d/da log(1.5 - |0.5 - a|) = sign(0.5 - a) / (1.5 - |0.5 - a|)
+            const float d = 0.5f - v.w;
+            const float sg = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
+            g.w += prior * (sg / (1.5f - fabsf(d)));
+        }
         if (grad_out) grad_out[(size_t)z * HW + p] = g;
         if (do_update) {
             v.x = fminf(fmaxf(v.x - lr_rgb * g.x, 0.0f), 1.0f);
@@ -1130,10 +1136,10 @@ __global__ __launch_bounds__(256) void k_update(void* __restrict__ mpi, int D, i
                                                 int cover_h, float lr_rgb, float lr_a, int do_update,
                                                 float4* __restrict__ grad_out,
                                                 const float* __restrict__ partials, int64_t nparts,
-                                                double loss_scale, float* __restrict__ out_loss) {
+                                                double loss_scale, float* __restrict__ out_loss, float prior) {
     extern __shared__ int2 s_off[];   // [nslices][D] (ix, iy) when SHIFT
     update_block<DT, SHIFT>(mpi, D, H, W, mask, kcap, slots, nslices, warps, cover_w, cover_h, lr_rgb, lr_a,
-                            do_update, grad_out, partials, nparts, loss_scale, out_loss, blockIdx.x, s_off);
+                            do_update, grad_out, partials, nparts, loss_scale, out_loss, prior, blockIdx.x, s_off);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1333,8 +1339,8 @@ __global__ __launch_bounds__(256) void k_batch_update(const BatchTable* __restri
         __syncthreads();                     // the previous item's shift table is no longer read
         update_block<DT, true>(b.mpi, b.D, b.H, b.W, b.mask, b.kcap, b.slots, b.N, b.warps, b.ntx * kOX,
                                b.nty * kOY, b.lr_rgb, b.lr_alpha, 1, nullptr, b.partials,
-                               (int64_t)b.ntx * b.nty * b.N, 0.5 / b.N, b.loss_out, g - t->pre[BK_UPDATE][sl],
-                               s_off);
+                               (int64_t)b.ntx * b.nty * b.N, 0.5 / b.N, b.loss_out, b.prior,
+                               g - t->pre[BK_UPDATE][sl], s_off);
     }
 }
 
@@ -1415,8 +1421,9 @@ int launch_render(const hsgd_mpi& m, const hsgd_views& v, float* out_rgb, float*
 }
 
 int launch_grad_step(const hsgd_mpi& m, const hsgd_views& v, const uint64_t* mask, int kcap,
-                     const float* dimg, float lr_rgb, float lr_alpha, float* grad_out, float* out_loss,
-                     float4* slots, float* partials, hipStream_t s) {
+                     const float* dimg, float lr_rgb, float lr_alpha, float lambda_s, float* grad_out,
+                     float* out_loss, float4* slots, float* partials, hipStream_t s) {
+    const float prior = (float)((double)lambda_s / ((double)m.D * m.H * m.W));
     const int HW = m.H * m.W;
     const float inv_n = 1.0f / (float)v.N;
     const bool shift = (v.flags & HSGD_VIEWS_SHIFT_ONLY) != 0;
@@ -1471,11 +1478,11 @@ int launch_grad_step(const hsgd_mpi& m, const hsgd_views& v, const uint64_t* mas
         HSGD_DISPATCH_T(m.dtype, if (shift) {
             hipLaunchKernelGGL((k_update<DT, true>), grid, dim3(256), lds, s, m.rgba, m.D, m.H, m.W, mask, kcap,
                                slots, v.N, v.warps, cover_w, cover_h, lr_rgb, lr_alpha, do_update,
-                               reinterpret_cast<float4*>(grad_out), partials, nparts, 0.5 / v.N, out_loss);
+                               reinterpret_cast<float4*>(grad_out), partials, nparts, 0.5 / v.N, out_loss, prior);
         } else {
             hipLaunchKernelGGL((k_update<DT, false>), grid, dim3(256), 0, s, m.rgba, m.D, m.H, m.W, mask, kcap,
                                slots, 1, v.warps, 0, 0, lr_rgb, lr_alpha, do_update,
-                               reinterpret_cast<float4*>(grad_out), partials, nparts, 0.5 / v.N, out_loss);
+                               reinterpret_cast<float4*>(grad_out), partials, nparts, 0.5 / v.N, out_loss, prior);
         });
     }
     return (int)hipGetLastError();

@@ -78,7 +78,8 @@ class Request(ctypes.Structure):
     _fields_ = [("stream_id", ctypes.c_int32), ("L", ctypes.c_int32),
                 ("levels", Mpi * MAX_BATCH_LEVELS), ("views", Views * MAX_BATCH_LEVELS),
                 ("iters", ctypes.c_int32 * MAX_BATCH_LEVELS), ("sel", SelectParams),
-                ("lr_rgb", ctypes.c_float), ("lr_alpha", ctypes.c_float), ("loss_log", ctypes.c_void_p)]
+                ("lr_rgb", ctypes.c_float), ("lr_alpha", ctypes.c_float), ("lambda_s", ctypes.c_float),
+                ("loss_log", ctypes.c_void_p)]
 
 # name -> (restype, argtypes); mirrors include/hsgd.h
 _P = ctypes.c_void_p
@@ -95,11 +96,11 @@ _SIGS = {
     "hsgd_select_active": (_I, [ctypes.POINTER(Mpi), SelectParams, _P, _P, _I, _P, _P, _P,
                                 ctypes.c_size_t, _P]),
     "hsgd_render": (_I, [ctypes.POINTER(Mpi), ctypes.POINTER(Views), _P, _P, _P, ctypes.c_size_t, _P]),
-    "hsgd_grad_step": (_I, [ctypes.POINTER(Mpi), ctypes.POINTER(Views), _P, _I, _P, _F, _F, _P, _P,
+    "hsgd_grad_step": (_I, [ctypes.POINTER(Mpi), ctypes.POINTER(Views), _P, _I, _P, _F, _F, _F, _P, _P,
                             _P, ctypes.c_size_t, _P]),
     "hsgd_upsample2x": (_I, [ctypes.POINTER(Mpi), ctypes.POINTER(Mpi), _P]),
     "hsgd_downsample2x": (_I, [_P, _I, _I, _I, _P, _P]),
-    "hsgd_refine": (_I, [ctypes.POINTER(Mpi), ctypes.POINTER(Views), _I, _P, SelectParams, _F, _F,
+    "hsgd_refine": (_I, [ctypes.POINTER(Mpi), ctypes.POINTER(Views), _I, _P, SelectParams, _F, _F, _F,
                          _P, _P, ctypes.c_size_t, _P]),
     "hsgd_convert": (_I, [_P, _I, _P, _I, ctypes.c_size_t, _P]),
     "hsgd_profile_begin": (_I, [ctypes.c_uint32]),
@@ -324,8 +325,9 @@ def hsgd_grad_step(rgba: torch.Tensor, warps: torch.Tensor, N: int, images: torc
                    mask: torch.Tensor | None = None, kcap: int | None = None,
                    dimg: torch.Tensor | None = None, lr_rgb: float = 0.0, lr_alpha: float = 0.0,
                    want_grad: bool = False, want_loss: bool = False, ws: torch.Tensor | None = None,
-                   stream=None):
-    """One sparse gradient step (in place on rgba when a learning rate is non-zero).
+                   stream=None, lambda_s: float = 0.0):
+    """One sparse gradient step (in place on rgba when a learning rate is non-zero), with
+    the sparsity prior lambda_s L_s added to the gradient when lambda_s != 0.
     Returns (grad [D][H][W][4] float32 or None, loss [1] or None)."""
     m = mpi_desc(rgba)
     v = views_desc(warps, N, m.H, m.W, images)
@@ -343,7 +345,7 @@ def hsgd_grad_step(rgba: torch.Tensor, warps: torch.Tensor, N: int, images: torc
     if ws is None:
         ws = workspace(OP_GRAD_STEP, m.D, m.H, m.W, N, kc, device=dev)
     _check(lib().hsgd_grad_step(ctypes.byref(m), ctypes.byref(v), _ptr(mask), kc, _ptr(dimg),
-                                float(lr_rgb), float(lr_alpha), _ptr(grad), _ptr(loss), _ptr(ws),
+                                float(lr_rgb), float(lr_alpha), float(lambda_s), _ptr(grad), _ptr(loss), _ptr(ws),
                                 ws.numel(), _stream(stream)))
     return grad, loss
 
@@ -416,9 +418,10 @@ class RefinePlan:
 
     def __init__(self, K_ref, K, R, t, depths, W: int, H: int, iters: Sequence[int], k: int,
                  tau: float = -1.0, lr_rgb: float = 1.0, lr_alpha: float = 1.0,
-                 dtype: torch.dtype = torch.float32, device="cuda", rule="topk"):
+                 dtype: torch.dtype = torch.float32, device="cuda", rule="topk", lambda_s: float = 0.0):
         L = len(iters)
         self.sel = select_params(k, tau, rule)
+        self.lambda_s = float(lambda_s)
         self.L, self.iters, self.k, self.tau = L, tuple(int(i) for i in iters), int(k), float(tau)
         self.lr_rgb, self.lr_alpha = float(lr_rgb), float(lr_alpha)
         self.N = int(np.asarray(K).reshape(-1, 3, 3).shape[0])
@@ -443,17 +446,18 @@ class RefinePlan:
         """Refine levels[0] (the initial MPI, already written by the caller) up to levels[-1]."""
         mpis, vs = descriptors or self.descriptors(images)
         _check(lib().hsgd_refine(mpis, vs, self.L, self._iters, self.sel,
-                                 self.lr_rgb, self.lr_alpha, _ptr(self.loss_log), _ptr(self.ws),
+                                 self.lr_rgb, self.lr_alpha, self.lambda_s, _ptr(self.loss_log), _ptr(self.ws),
                                  self.ws.numel(), _stream(stream)))
         return self.levels[-1]
 
 
 def hsgd_refine(init: torch.Tensor, images: torch.Tensor, K_ref, K, R, t, depths, iters, k,
-                tau: float = -1.0, lr_rgb: float = 1.0, lr_alpha: float = 1.0, stream=None, rule="topk"):
+                tau: float = -1.0, lr_rgb: float = 1.0, lr_alpha: float = 1.0, stream=None, rule="topk",
+                lambda_s: float = 0.0):
     """One-shot refinement: returns (final MPI, per-iteration losses)."""
     N, H, W, _ = images.shape
     plan = RefinePlan(K_ref, K, R, t, depths, W, H, iters, k, tau, lr_rgb, lr_alpha,
-                      dtype=init.dtype, device=init.device, rule=rule)
+                      dtype=init.dtype, device=init.device, rule=rule, lambda_s=lambda_s)
     plan.levels[0].copy_(init)
     plan.run(images, stream=stream)
     return plan.levels[-1], plan.loss_log[:sum(plan.iters)]
@@ -470,7 +474,7 @@ class ServingStream:
 
     def __init__(self, stream_id: int, K_ref, K, R, t, depths, W: int, H: int, iters: Sequence[int], k: int,
                  dtype: torch.dtype = torch.bfloat16, tau: float = -1.0, lr_rgb: float = 1.0,
-                 lr_alpha: float = 1.0, device="cuda", rule="topk"):
+                 lr_alpha: float = 1.0, device="cuda", rule="topk", lambda_s: float = 0.0):
         L = len(iters)
         if L > MAX_BATCH_LEVELS:
             raise ValueError(f"at most {MAX_BATCH_LEVELS} levels")
@@ -491,7 +495,7 @@ class ServingStream:
             req.views[l] = views_desc(self.warps[l], self.N, h, w, self.images[l])
             req.iters[l] = self.iters[l]
         req.sel = select_params(self.k, tau, rule)
-        req.lr_rgb, req.lr_alpha = float(lr_rgb), float(lr_alpha)
+        req.lr_rgb, req.lr_alpha, req.lambda_s = float(lr_rgb), float(lr_alpha), float(lambda_s)
         req.loss_log = _ptr(self.loss_log)
         self.request = req
 

@@ -135,11 +135,12 @@ def test_validation_status_codes():
     assert L.hsgd_render(by(_mpi()), by(_views()), None, FAKE, None, 0, None) == -5
     # grad_step
     gs = L.hsgd_grad_step
-    assert gs(by(_mpi()), by(_views(images=None)), None, 8, None, 0.0, 0.0, FAKE, None, FAKE, 1 << 30, None) == -1
-    assert gs(by(_mpi()), by(_views()), FAKE, 0, None, 0.0, 0.0, FAKE, None, FAKE, 1 << 30, None) == -1
-    assert gs(by(_mpi()), by(_views()), FAKE, 9, None, 0.0, 0.0, FAKE, None, FAKE, 1 << 30, None) == -1
-    assert gs(by(_mpi()), by(_views()), FAKE, 2, None, float("inf"), 0.0, FAKE, None, FAKE, 1 << 30, None) == -1
-    assert gs(by(_mpi()), by(_views()), FAKE, 2, None, 0.0, 0.0, FAKE, None, FAKE, 64, None) == -5
+    assert gs(by(_mpi()), by(_views(images=None)), None, 8, None, 0.0, 0.0, 0.0, FAKE, None, FAKE, 1 << 30, None) == -1
+    assert gs(by(_mpi()), by(_views()), FAKE, 0, None, 0.0, 0.0, 0.0, FAKE, None, FAKE, 1 << 30, None) == -1
+    assert gs(by(_mpi()), by(_views()), FAKE, 9, None, 0.0, 0.0, 0.0, FAKE, None, FAKE, 1 << 30, None) == -1
+    assert gs(by(_mpi()), by(_views()), FAKE, 2, None, float("inf"), 0.0, 0.0, FAKE, None, FAKE, 1 << 30, None) == -1
+    assert gs(by(_mpi()), by(_views()), FAKE, 2, None, 0.0, 0.0, 0.0, FAKE, None, FAKE, 64, None) == -5
+    assert gs(by(_mpi()), by(_views()), FAKE, 2, None, 0.0, 0.0, float("nan"), FAKE, None, FAKE, 1 << 30, None) == -1
     # up/downsample, convert
     assert L.hsgd_upsample2x(by(_mpi()), by(_mpi(H=16, W=32, ptr=0x2000)), None) == -2
     assert L.hsgd_upsample2x(by(_mpi()), by(_mpi(H=32, W=32, dtype=1, ptr=0x2000)), None) == -3
@@ -152,15 +153,19 @@ def test_validation_status_codes():
     it = (ctypes.c_int32 * 2)(1, 1)
     lv = (hsgd.Mpi * 2)(_mpi(H=8, W=8), _mpi(H=16, W=16, ptr=0x2000))
     vs = (hsgd.Views * 2)(_views(H=8, W=8, images=None), _views())
-    assert L.hsgd_refine(lv, vs, 2, it, sp(2, -1), 1.0, 1.0, None, FAKE, 64, None) == -5
-    assert L.hsgd_refine(lv, vs, 0, it, sp(2, -1), 1.0, 1.0, None, FAKE, 1 << 30, None) == -1
-    assert L.hsgd_refine(lv, vs, 2, it, sp(9, -1), 1.0, 1.0, None, FAKE, 1 << 30, None) == -1
+    assert L.hsgd_refine(lv, vs, 2, it, sp(2, -1), 1.0, 1.0, 0.0, None, FAKE, 64, None) == -5
+    assert L.hsgd_refine(lv, vs, 0, it, sp(2, -1), 1.0, 1.0, 0.0, None, FAKE, 1 << 30, None) == -1
+    assert L.hsgd_refine(lv, vs, 2, it, sp(9, -1), 1.0, 1.0, 0.0, None, FAKE, 1 << 30, None) == -1
     bad = (hsgd.Mpi * 2)(_mpi(H=8, W=8), _mpi(H=16, W=18, ptr=0x2000))
-    assert L.hsgd_refine(bad, vs, 2, it, sp(2, -1), 1.0, 1.0, None, FAKE, 1 << 30, None) == -2
+    assert L.hsgd_refine(bad, vs, 2, it, sp(2, -1), 1.0, 1.0, 0.0, None, FAKE, 1 << 30, None) == -2
     neg = (ctypes.c_int32 * 2)(1, -1)
-    assert L.hsgd_refine(lv, vs, 2, neg, sp(2, -1), 1.0, 1.0, None, FAKE, 1 << 30, None) == -1
+    assert L.hsgd_refine(lv, vs, 2, neg, sp(2, -1), 1.0, 1.0, 0.0, None, FAKE, 1 << 30, None) == -1
     novs = (hsgd.Views * 2)(_views(H=8, W=8, images=None), _views(images=None))
-    assert L.hsgd_refine(lv, novs, 2, it, sp(2, -1), 1.0, 1.0, None, FAKE, 1 << 30, None) == -1
+    assert L.hsgd_refine(lv, novs, 2, it, sp(2, -1), 1.0, 1.0, 0.0, None, FAKE, 1 << 30, None) == -1
+    # an unknown selection rule and a non-finite prior weight are argument errors
+    assert L.hsgd_refine(lv, vs, 2, it, sp(2, -1, 7), 1.0, 1.0, 0.0, None, FAKE, 1 << 30, None) == -1
+    assert L.hsgd_refine(lv, vs, 2, it, sp(2, -1), 1.0, 1.0, float("nan"), None, FAKE, 1 << 30, None) == -1
+    assert L.hsgd_select_active(by(_mpi()), sp(2, -1, 2), FAKE, None, 0, None, None, None, 0, None) == -1
     assert hsgd.lib().hsgd_last_error().decode() != ""
 
 

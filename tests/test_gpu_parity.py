@@ -370,3 +370,53 @@ def test_shift_path_large_shifts_and_borders():
     _, g_ref = O.loss_and_grad(M, oracle_maps(O, rg), I)
     g, _ = hsgd.hsgd_grad_step(to_dev(M), device_warps(hsgd, rg), N, images=to_dev(I), want_grad=True)
     assert rel_err(g.cpu().numpy(), g_ref) <= GRAD_RTOL
+
+
+# --------------------------------------------------------------------------------- sparsity prior
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16], ids=["fp32", "bf16"])
+def test_update_step_with_sparsity_prior(dtype):
+    """The prior lambda_s L_s of Sec. 3.4 in the step: the oracle's dense gradient plus
+    lambda_s dL_s/dalpha, restricted to S; the weight makes the prior comparable to the
+    data term (0.2 per voxel)."""
+    D, W, H = 16, 96, 72
+    rg, M, I = problem(33, 3, D, W, H, 60.0, 0.08, lo=0.05, hi=0.95)
+    k, lr, lam = 4, 0.5, 0.2 * D * H * W
+    bf = dtype == torch.bfloat16
+    Mq = bf16_vals(M) if bf else M
+    Md = to_dev(M, dtype)
+    mask = hsgd.hsgd_select_active(Md, k, with_ids=False)
+    S = mask_bits(mask.cpu().numpy(), D)
+    _, g_ref = O.loss_and_grad(Mq, oracle_maps(O, rg), I)
+    g_ref[..., 3] += lam * O.sparsity_grad(Mq[..., 3])
+    g, _ = hsgd.hsgd_grad_step(Md, device_warps(hsgd, rg), 3, images=to_dev(I), mask=mask, kcap=k,
+                               want_grad=True, lambda_s=lam)
+    g = g.cpu().numpy()
+    assert np.all(g[~S] == 0.0)
+    assert rel_err(g[S], g_ref[S]) <= GRAD_RTOL
+    hsgd.hsgd_grad_step(Md, device_warps(hsgd, rg), 3, images=to_dev(I), mask=mask, kcap=k,
+                        lr_rgb=lr, lr_alpha=lr, lambda_s=lam)
+    got = Md.float().cpu().numpy()
+    ref = O.apply_update(Mq, g_ref, S, lr, lr, bf16=bf)
+    assert np.all(got[~S] == Mq[~S])
+    if bf:
+        diff = np.abs(got - ref)
+        assert np.mean(diff > 0) < 1e-3 and diff.max() <= 2.0 ** -8
+    else:
+        assert np.abs(got - ref).max() <= 1e-5
+
+
+def test_refine_with_sparsity_prior_matches_oracle():
+    sc, init, targets = scene_inputs("c1")
+    lam = 0.2 * sc.D * sc.H * sc.W
+    M_ref, log = O.refine(init, targets, sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(),
+                          sc.depths, sc.iters, sc.k, 1.0, 1.0, lambda_s=lam)
+    final, losses = hsgd.hsgd_refine(to_dev(init), to_dev(targets), sc.K_ref(), sc.K_views(), sc.R_views(),
+                                     sc.t_views(), sc.depths, sc.iters, sc.k, lambda_s=lam)
+    np.testing.assert_allclose(losses.cpu().numpy(), [e["loss"] for e in log], rtol=1e-4)
+    assert np.abs(final.cpu().numpy() - M_ref).max() <= 1e-3
+    # the prior moves the refined alphas towards 0 and 1 relative to no prior
+    plain, _ = hsgd.hsgd_refine(to_dev(init), to_dev(targets), sc.K_ref(), sc.K_views(), sc.R_views(),
+                                sc.t_views(), sc.depths, sc.iters, sc.k)
+    a_p = final[..., 3].cpu().numpy()
+    a_0 = plain[..., 3].cpu().numpy()
+    assert np.mean(np.abs(a_p - 0.5)) > np.mean(np.abs(a_0 - 0.5))

@@ -167,3 +167,21 @@ def test_mvs_rule_request_equals_refine(mix):
                               sc.depths, sc.iters, 5, rule="mvs")
     assert torch.equal(st_m.result, ref)
     assert not torch.equal(st_m.result, st.result)
+
+
+def test_sparsity_prior_request_equals_refine(mix):
+    si = mix[0]
+    sc = si.sc
+    lam = 0.1 * sc.D * sc.H * sc.W
+    st = hsgd.ServingStream(0, sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths, sc.W, sc.H,
+                            sc.iters, sc.k, lambda_s=lam)
+    st.images[-1].copy_(si.targets)
+    st.levels[0].copy_(si.inits[1])
+    b = hsgd.Batch(1, sc.D, sc.N, sc.H, sc.W, sc.k)
+    assert b.admit(st) is not None
+    while b.step()[0]:
+        pass
+    torch.cuda.synchronize()
+    ref, _ = hsgd.hsgd_refine(si.inits[1], si.targets, sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(),
+                              sc.depths, sc.iters, sc.k, lambda_s=lam)
+    assert torch.equal(st.result, ref)

@@ -337,6 +337,27 @@ def test_mvs_window_of_one_opaque_plane():
         assert list(np.flatnonzero(m)) == list(range(lo, lo + k)), (z0, np.flatnonzero(m))
 
 
+def test_sparsity_prior_gradient_against_finite_differences():
+    # L_s (Sec. 3.4) is smooth away from alpha = 0.5: its central differences match the
+    # closed-form gradient; descent pushes alpha towards 0 below 0.5 and towards 1 above
+    rng = RNG(70)
+    a = rng.uniform(size=(4, 3, 5))
+    a = np.where(np.abs(a - 0.5) < 0.02, a + 0.05, a)
+    g = O.sparsity_grad(a)
+    h = 1e-6
+    for idx in [(0, 0, 0), (1, 2, 3), (3, 1, 4), (2, 0, 2)]:
+        ap, am = a.copy(), a.copy()
+        ap[idx] += h
+        am[idx] -= h
+        fd = (O.sparsity_loss(ap) - O.sparsity_loss(am)) / (2 * h)
+        assert abs(fd - g[idx]) <= 1e-7 * max(1.0, abs(g[idx])) + 1e-12
+    assert np.all(np.sign(g) == np.sign(0.5 - a))
+    # values the definition fixes: log(1) = 0 at alpha in {0, 1}, log(1.5) at 0.5
+    assert O.sparsity_loss(np.array([0.0, 1.0])) == 0.0
+    assert abs(O.sparsity_loss(np.array([0.5])) - np.log(1.5)) < 1e-15
+    assert O.sparsity_grad(np.array([0.5, 0.0, 1.0])).tolist() == [0.0, 1.0 / 3.0, -1.0 / 3.0]
+
+
 def test_select_scores_follow_eq_gradient():
     # A_z = a_z prod_{j<z}(1 - a_j), the paper's alpha gradient on the reference view
     rng = RNG(31)
