@@ -23,6 +23,8 @@ Everything follows the paper (RealLiFe, arXiv 2307.03017) in its own order and n
   voxels, M <- clip(M - lambda * dL/dM, 0, 1) on S, unchanged elsewhere.
 * Hierarchy (Sec. 3.2 / 3.3): levels at H/2^l x W/2^l, coarse to fine, the MPI upsampled
   between levels.
+* Plane-sweep volume (Sec. 3.2, Hierarchical PSV Construction): every source image
+  sampled on every reference plane through H_i^{-1}(d), then box-downsampled level by level.
 
 Readings where the paper is silent (each listed in the design notes):
   bilinear sampling in pixel-index coordinates with zero padding, colour and alpha
@@ -46,6 +48,7 @@ __all__ = [
     "render_view", "render", "photometric_loss", "loss_and_grad", "render_vjp",
     "select_scores_f32", "select_active", "select_ids", "apply_update", "bf16_round",
     "upsample2x", "downsample2x", "target_pyramid", "psnr", "refine",
+    "plane_sweep", "psv_pyramid",
 ]
 
 
@@ -358,6 +361,32 @@ def target_pyramid(targets, levels):
     for _ in range(levels - 1):
         pyr.append(downsample2x(pyr[-1]))
     return pyr[::-1]
+
+
+# --------------------------------------------------------------------------------------
+# Plane-sweep volume: Sec. 3.2 (Hierarchical PSV Construction)
+# --------------------------------------------------------------------------------------
+def plane_sweep(images, K_r, K, R, t, depths):
+    """P[i][z] = I_i^{w^-1}(., ., d_z): source image i grid-sampled at the reference meshgrid
+    carried by H_i^{-1}(d_z) of Eq. (homo), for every view i and plane z. images [N][H][W][3];
+    the reference grid has the images' size. Returns [N][D][H][W][3] (the paper's
+    N x D x H x W x 3)."""
+    images = np.asarray(images, float)
+    N, H, W, _ = images.shape
+    P = np.empty((N, len(depths), H, W, 3))
+    for i in range(N):
+        for z, d in enumerate(depths):
+            P[i, z] = sample_bilinear(images[i], plane_homography(K_r, K[i], R[i], t[i], d))
+    return P
+
+
+def psv_pyramid(P, levels):
+    """The hierarchy of plane-sweep volumes: level 0 is P itself, level l the 2x2 box mean of
+    level l - 1 over the spatial axes (H/2^l x W/2^l), finest first."""
+    pyr = [np.asarray(P, float)]
+    for _ in range(levels - 1):
+        pyr.append(downsample2x(pyr[-1]))
+    return pyr
 
 
 def refine(M0, targets, K_r, K, R, t, depths, iters, k, lr_rgb, lr_alpha, tau=-1.0,

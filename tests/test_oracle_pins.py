@@ -444,6 +444,111 @@ def test_downsample_box_mean():
     np.testing.assert_allclose(d.sum() * 4, img.sum())
 
 
+# ------------------------------------------------------------------ plane-sweep volume
+def test_plane_sweep_identity_pose_copies_every_image_onto_every_plane():
+    rng = RNG(40)
+    I = rng.uniform(size=(2, 9, 11, 3))
+    K = np.array([[20.0, 0.0, 5.0], [0.0, 20.0, 4.0], [0, 0, 1]])
+    P = O.plane_sweep(I, K, np.stack([K, K]), np.stack([np.eye(3)] * 2), np.zeros((2, 3)),
+                      np.array([1.0, 2.5, 7.0]))
+    assert P.shape == (2, 3, 9, 11, 3)
+    for z in range(3):
+        np.testing.assert_array_equal(P[:, z], I)
+
+
+def test_plane_sweep_integer_disparity_is_a_shifted_copy_with_zero_borders():
+    # pure translation: the reference pixel (x, y) on plane d sees source pixel
+    # (x + f t_x / d, y + f t_y / d); with integer disparities the PSV is a plain shifted
+    # copy, brute-forced here pixel by pixel
+    rng = RNG(41)
+    H, W, f = 7, 10, 12.0
+    I = rng.uniform(size=(1, H, W, 3))
+    K = np.array([[f, 0.0, 4.5], [0.0, f, 3.0], [0, 0, 1]])
+    t = np.array([[0.5, -0.25, 0.0]])
+    P = O.plane_sweep(I, K, K[None], np.eye(3)[None], t, np.array([3.0]))
+    dx, dy = 2, -1                                          # f t / d at d = 3
+    expect = np.zeros((H, W, 3))
+    for y in range(H):
+        for x in range(W):
+            if 0 <= x + dx < W and 0 <= y + dy < H:
+                expect[y, x] = I[0, y + dy, x + dx]
+    np.testing.assert_array_equal(P[0, 0], expect)
+
+
+def test_plane_sweep_samples_linear_images_at_the_projected_point():
+    # Source images that are linear in their own pixel coordinates: wherever the four taps
+    # lie inside, the PSV value is that linear function at the projection of the 3D point
+    # on plane d behind reference pixel (u, v), constructed explicitly (back-project, move,
+    # project) for a rotating, zooming, z-translating rig. Pins the direction of the map
+    # (reference -> source, not its inverse) and the sampling.
+    rng = RNG(42)
+    H, W = 14, 18
+    Kr = np.array([[16.0, 0.0, 8.5], [0.0, 15.0, 6.5], [0, 0, 1]])
+    K = np.stack([np.array([[14.0, 0.0, 9.0], [0.0, 14.5, 6.0], [0, 0, 1]]),
+                  np.array([[17.0, 0.0, 8.0], [0.0, 16.0, 7.0], [0, 0, 1]])])
+    R = np.stack([_rot(0.03, -0.05, 0.08), _rot(-0.04, 0.02, -0.06)])
+    t = rng.normal(size=(2, 3)) * 0.1
+    depths = np.array([1.5, 4.0])
+    ys, xs = np.mgrid[0:H, 0:W].astype(float)
+    coef = [(0.3, -0.2, 1.0), (-0.1, 0.4, 0.5), (0.05, 0.05, -0.3)]
+    I = np.stack([np.stack([a * xs + b * ys + c + 0.7 * i for a, b, c in coef], axis=-1)
+                  for i in range(2)])
+    P = O.plane_sweep(I, Kr, K, R, t, depths)
+    checked = 0
+    for i in range(2):
+        for z, d in enumerate(depths):
+            for v in range(H):
+                for u in range(W):
+                    X = d * np.linalg.solve(Kr, [u, v, 1.0])
+                    p = K[i] @ (R[i] @ X + t[i])
+                    x, y = p[0] / p[2], p[1] / p[2]
+                    if 0 <= x <= W - 1 and 0 <= y <= H - 1:
+                        exp = [a * x + b * y + c + 0.7 * i for a, b, c in coef]
+                        np.testing.assert_allclose(P[i, z, v, u], exp, atol=1e-10)
+                        checked += 1
+    assert checked > H * W                                  # most of the grid is inside
+
+
+def test_plane_sweep_is_photo_consistent_at_the_true_depth():
+    # One opaque textured plane at depth d_3: the source views are its renders; sweeping
+    # them back, every view reproduces the texture on plane 3 (inside the overlap, integer
+    # disparities: exactly), and the views disagree on the other planes.
+    rng = RNG(43)
+    H, W, D, f = 12, 16, 5, 8.0
+    depths = np.array([1.0, 1.5, 2.0, 4.0, 8.0])
+    K = np.array([[f, 0.0, 7.5], [0.0, f, 5.5], [0, 0, 1]])
+    t = np.array([[0.5, 0.0, 0.0], [-0.5, 0.5, 0.0], [0.0, -1.0, 0.0]])     # f t / 4: 1, 1, 2 px
+    N = len(t)
+    Ks, Rs = np.stack([K] * N), np.stack([np.eye(3)] * N)
+    tex = rng.uniform(size=(H, W, 3))
+    M = np.zeros((D, H, W, 4))
+    M[3, ..., :3] = tex
+    M[3, ..., 3] = 1.0
+    views = O.render(M, O.view_to_ref_maps(K, Ks, Rs, t, depths))
+    P = O.plane_sweep(views, K, Ks, Rs, t, depths)
+    inner = (slice(2, H - 2), slice(2, W - 2))
+    for i in range(N):
+        np.testing.assert_allclose(P[i, 3][inner], tex[inner], atol=1e-12)
+    spread = lambda z: P[:, z][(slice(None),) + inner].std(axis=0).mean()
+    assert spread(3) < 1e-12
+    assert min(spread(z) for z in (0, 1, 2, 4)) > 0.05
+
+
+def test_psv_pyramid_levels_are_block_means():
+    rng = RNG(44)
+    P = rng.uniform(size=(2, 3, 8, 12, 3))
+    pyr = O.psv_pyramid(P, 3)
+    assert [q.shape for q in pyr] == [(2, 3, 8, 12, 3), (2, 3, 4, 6, 3), (2, 3, 2, 3, 3)]
+    np.testing.assert_array_equal(pyr[0], P)
+    for l in (1, 2):
+        s = 2 ** l
+        for y in range(8 // s):
+            for x in range(12 // s):
+                np.testing.assert_allclose(pyr[l][:, :, y, x],
+                                           P[:, :, s * y:s * y + s, s * x:s * x + s].mean(axis=(2, 3)),
+                                           atol=1e-14)
+
+
 # ------------------------------------------------------------------ whole refine
 def test_refine_decreases_loss_on_tiny_scene():
     sc = scenes.make_scene("c1")
