@@ -39,10 +39,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=None, help="default 10 refines (100 requests for serving)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c5", "serving", "views18"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c5", "serving", "views18", "psv", "psv5"],
                     help="c2: 512x384x32 (the headline), c1: 64x48x8, c5: 1920x1080x64 8 views, "
                          "serving: the continuous-batching mix under Poisson arrivals, "
-                         "views18: 18 novel views of a refined 512x384x32 MPI per step")
+                         "views18: 18 novel views of a refined 512x384x32 MPI per step, "
+                         "psv / psv5: the 3-level plane-sweep volume of the c2 rig / the 4-level "
+                         "one of the c5 rig per step")
     ap.add_argument("--requests", type=int, default=1200, help="serving: measured requests")
     ap.add_argument("--rate", type=float, default=60.0, help="serving: mean arrivals per second")
     ap.add_argument("--dtype", default=None, choices=["fp32", "bf16"],
@@ -335,6 +337,115 @@ def views_cpu_baseline():
             "sample": f"3 of the 18 novel views of a {sc.W}x{sc.H}x{sc.D} MPI (FP64 NumPy, {dt:.1f} s)"}
 
 
+PSV_RIGS = {"psv": ("c2", 3), "psv5": ("c5", 4)}
+
+
+def psv_bench(args):
+    """Hierarchical plane-sweep volume: per step one hsgd_plane_sweep of the rig's N source
+    images (the ground truth rendered into each view) onto its D planes, all levels stored
+    ([N][D][H>>l][W>>l][3] FP32)."""
+    import torch
+
+    from paper_2307_03017_amd import hsgd, scenes
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg, L = PSV_RIGS[args.workload]
+    sc = scenes.make_scene(cfg)
+    gt = torch.from_numpy(sc.gt_mpi(np.float32)).to(dev)
+    views = hsgd.level_warps(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths,
+                             sc.W, sc.H, sc.W, sc.H, dev)
+    images, _ = hsgd.hsgd_render(gt, views, sc.N)
+    del gt
+    table = hsgd.psv_warps(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths, dev)
+    out = hsgd.hsgd_plane_sweep(images, table, sc.D, L)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        hsgd.hsgd_plane_sweep(images, table, sc.D, L, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    steps = args.steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[i][0].record(stream)
+        step()
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    with hsgd.KernelTimer([hsgd.K_PSV]) as kt:
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+    n_k, ms_k = kt.result[hsgd.K_PSV]
+    HW = sc.H * sc.W
+    samples = sc.N * sc.D * HW
+    wr = sum(samples // 4 ** l * 12 for l in range(L))
+    alg_bytes = sc.N * HW * 12 + wr                 # images read once, every level written once
+    t_launch = ms_k * 1e-3 / max(n_k, 1)
+    gbs = alg_bytes / t_launch / 1e9
+    res = {
+        "metric": f"plane-sweep volume samples/s ({sc.W}x{sc.H}, {sc.D} planes, {sc.N} views, {L} levels)",
+        "value": samples * steps / wall,
+        "unit": "PSV samples/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": (f"hsgd_plane_sweep of {sc.N} {sc.W}x{sc.H} source images onto {sc.D} "
+                                f"planes, {L} levels {'->'.join(f'{sc.W >> l}x{sc.H >> l}' for l in range(L))}, "
+                                f"translation rig"),
+                   "bytes_written_per_step": wr},
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "roofline": {
+            "kernel": "k_plane_sweep",
+            "bound": "hbm",
+            "achieved": gbs,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS,
+            "traffic": None,
+            "launches": n_k,
+            "avg_launch_us": t_launch * 1e6,
+            "alg_bytes_per_launch": alg_bytes,
+        },
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = psv_cpu_baseline(cfg, L)
+    print(json.dumps(res), flush=True)
+
+
+def psv_cpu_baseline(cfg, L):
+    """The FP64 oracle building a bounded part of the plane-sweep volume (c2: every view and
+    plane; c5: 16 planes of view 0) with its levels, single-threaded, scaled to samples/s."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import hsgd_oracle as O
+    from paper_2307_03017_amd import scenes
+
+    sc = scenes.make_scene(cfg)
+    nv, planes = (sc.N, sc.D) if cfg == "c2" else (1, 16)
+    I = np.random.default_rng(3).uniform(size=(nv, sc.H, sc.W, 3))
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        P = O.plane_sweep(I, sc.K_ref(), sc.K_views()[:nv], sc.R_views()[:nv], sc.t_views()[:nv],
+                          sc.depths[:planes])
+        O.psv_pyramid(P, L)
+        dt = time.perf_counter() - t0
+    return {"value": nv * planes * sc.H * sc.W / dt, "unit": "PSV samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nv} view(s) x {planes} planes, {L} levels at {sc.W}x{sc.H} (FP64 NumPy, {dt:.1f} s)"}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -350,6 +461,9 @@ def main():
     if args.workload == "views18":
         args.dtype = args.dtype or "fp32"
         views_bench(args)
+        return
+    if args.workload in PSV_RIGS:
+        psv_bench(args)
         return
 
     import torch

@@ -133,6 +133,17 @@ hsgd_status hsgd_build_warps(const double* K_ref, const double* K, const double*
                              const double* t, const double* depth, int32_t N, int32_t D,
                              hsgd_warp* out);
 
+/*
+ * hsgd_build_psv_warps -- host, FP64 (Sec. 3.2, Eq. homo): the plane-sweep direction.
+ * out[i*D + z] holds H_i^{-1}(d_z) itself, the map from a reference pixel on plane z to
+ * source view i (hsgd_build_warps stores its inverse), normalised by |G[8]| and split into
+ * an exact integer + fraction translation when it is one, as hsgd_build_warps does.
+ * Arguments, ownership and errors as for hsgd_build_warps.
+ */
+hsgd_status hsgd_build_psv_warps(const double* K_ref, const double* K, const double* R,
+                                 const double* t, const double* depth, int32_t N, int32_t D,
+                                 hsgd_warp* out);
+
 /* hsgd_warps_shift_only -- host. 1 if all n records (host memory) are pure translations,
  * else 0 (also for NULL or n < 1): the value for hsgd_views.flags. */
 int32_t hsgd_warps_shift_only(const hsgd_warp* warps, int32_t n);
@@ -228,6 +239,26 @@ hsgd_status hsgd_upsample2x(const hsgd_mpi* coarse, hsgd_mpi* fine, hipStream_t 
  */
 hsgd_status hsgd_downsample2x(const float* images, int32_t N, int32_t H, int32_t W,
                               float* out, hipStream_t stream);
+
+/*
+ * hsgd_plane_sweep -- the hierarchical plane-sweep volume (Sec. 3.2, Hierarchical PSV
+ * Construction): level 0 is P[i][z][y][x] = bilinear sample of source image i at
+ * H_i^{-1}(d_z) (x, y, 1) (pixel-index coordinates, zero padding outside the image, 0 where
+ * the point is behind view i), for every view i, plane z and reference pixel (x, y) of an
+ * H x W reference grid; level l (1 <= l < L) is the 2x2 box mean of level l - 1
+ * (H/2^l x W/2^l). All levels come from one pass over the images: no level is re-read.
+ *  src    images: device [N][H][W][3] FP32 source images (required); warps: device [N][D]
+ *         records from hsgd_build_psv_warps for an H x W reference camera; flags
+ *         HSGD_VIEWS_SHIFT_ONLY as for the other calls (translation path).
+ *  D      planes, 1..64; L levels, 1..5; H and W multiples of 2^(L-1).
+ *  out    host array of L device pointers, 16-byte aligned: out[l] receives
+ *         [N][D][H>>l][W>>l][3] FP32; a NULL entry skips storing that level (at least one
+ *         must be set). Caller owns all buffers; no workspace.
+ * Errors: HSGD_E_ARG (NULL images/warps/out, every out[l] NULL, misaligned out),
+ *         HSGD_E_SHAPE (N, D, L, H, W out of range), HSGD_E_HIP (launch failure).
+ */
+hsgd_status hsgd_plane_sweep(const hsgd_views* src, int32_t D, int32_t L, float* const* out,
+                             hipStream_t stream);
 
 /*
  * hsgd_refine -- the whole coarse-to-fine HSGD refinement (Sec. 3.3; Fig. pipeline).
@@ -353,7 +384,7 @@ int64_t hsgd_batch_budget_used(const hsgd_batch* b);
 enum {
     HSGD_K_SELECT = 0, HSGD_K_SCAN = 1, HSGD_K_COMPACT = 2, HSGD_K_RENDER = 3,
     HSGD_K_GRAD = 4, HSGD_K_UPDATE = 5, HSGD_K_FILL = 6, HSGD_K_REDUCE = 7,
-    HSGD_K_UPSAMPLE = 8, HSGD_K_DOWNSAMPLE = 9, HSGD_K_CONVERT = 10, HSGD_K_COUNT = 11
+    HSGD_K_UPSAMPLE = 8, HSGD_K_DOWNSAMPLE = 9, HSGD_K_CONVERT = 10, HSGD_K_PSV = 11, HSGD_K_COUNT = 12
 };
 hsgd_status hsgd_profile_begin(uint32_t kind_mask);
 hsgd_status hsgd_profile_end(void);

@@ -107,6 +107,29 @@ hsgd_status hsgd_downsample2x(const float* images, int32_t N, int32_t H, int32_t
     return hip_status(launch_downsample(images, N, H, W, out, stream), fn);
 }
 
+hsgd_status hsgd_plane_sweep(const hsgd_views* src, int32_t D, int32_t L, float* const* out,
+                             hipStream_t stream) {
+    clear_error();
+    const char* fn = "hsgd_plane_sweep";
+    if (!src || !out) return fail(HSGD_E_ARG, "%s: NULL pointer", fn);
+    if (!src->images || !src->warps) return fail(HSGD_E_ARG, "%s: images or warps are NULL", fn);
+    if (src->N < 1 || src->N > kMaxN || D < 1 || D > kMaxD)
+        return fail(HSGD_E_SHAPE, "%s: N=%d or D=%d out of range", fn, src->N, D);
+    if (L < 1 || L > kPsvMaxL) return fail(HSGD_E_SHAPE, "%s: L=%d outside [1, %d]", fn, L, kPsvMaxL);
+    const int s = 1 << (L - 1);
+    if (src->H < 1 || src->W < 1 || src->H % s || src->W % s)
+        return fail(HSGD_E_SHAPE, "%s: %dx%d is not a positive multiple of 2^(L-1) = %d", fn, src->W, src->H, s);
+    if ((int64_t)src->N * D * ((src->W + 63) / 64) * ((src->H + 15) / 16) > INT32_MAX)
+        return fail(HSGD_E_SHAPE, "%s: volume too large for one launch", fn);
+    bool any = false;
+    for (int l = 0; l < L; ++l) {
+        if ((uintptr_t)out[l] % 16) return fail(HSGD_E_ARG, "%s: out[%d] is not 16-byte aligned", fn, l);
+        any = any || out[l];
+    }
+    if (!any) return fail(HSGD_E_ARG, "%s: every output level is NULL", fn);
+    return hip_status(launch_plane_sweep(*src, D, L, out, stream), fn);
+}
+
 hsgd_status hsgd_convert(const void* src, int32_t src_dtype, void* dst, int32_t dst_dtype,
                          size_t n, hipStream_t stream) {
     clear_error();

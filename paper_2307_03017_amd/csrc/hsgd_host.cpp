@@ -216,19 +216,22 @@ hsgd_status hsgd_level_intrinsics(const double* K, int32_t W, int32_t H, int32_t
     return HSGD_OK;
 }
 
-hsgd_status hsgd_build_warps(const double* K_ref, const double* K, const double* R,
-                             const double* t, const double* depth, int32_t N, int32_t D,
-                             hsgd_warp* out) {
+// Per (view, plane) maps of Eq. (homo): view pixel -> reference pixel (to_reference, the
+// direction rendering gathers in) or reference pixel -> view pixel (the plane-sweep
+// direction), as hsgd_warp records with the exact integer + fraction split of translations.
+static hsgd_status build_maps(const double* K_ref, const double* K, const double* R, const double* t,
+                              const double* depth, int32_t N, int32_t D, hsgd_warp* out, bool to_reference,
+                              const char* fn) {
     clear_error();
     if (!K_ref || !K || !R || !t || !depth || !out)
-        return fail(HSGD_E_ARG, "hsgd_build_warps: NULL pointer");
+        return fail(HSGD_E_ARG, "%s: NULL pointer", fn);
     if (N < 1 || N > kMaxN || D < 1 || D > kMaxD)
-        return fail(HSGD_E_SHAPE, "hsgd_build_warps: N=%d or D=%d out of range", N, D);
+        return fail(HSGD_E_SHAPE, "%s: N=%d or D=%d out of range", fn, N, D);
     double Kr_inv[9];
-    if (!mat3_inv(K_ref, Kr_inv)) return fail(HSGD_E_ARG, "hsgd_build_warps: K_ref is singular");
+    if (!mat3_inv(K_ref, Kr_inv)) return fail(HSGD_E_ARG, "%s: K_ref is singular", fn);
     for (int z = 0; z < D; ++z)
         if (!(depth[z] > 0.0) || !std::isfinite(depth[z]))
-            return fail(HSGD_E_ARG, "hsgd_build_warps: depth[%d] = %g is not positive", z, depth[z]);
+            return fail(HSGD_E_ARG, "%s: depth[%d] = %g is not positive", fn, z, depth[z]);
     hsgd_warp* tmp = new hsgd_warp[(size_t)N * D];
     for (int i = 0; i < N; ++i) {
         const double* Ki = K + 9 * i;
@@ -243,9 +246,12 @@ hsgd_status hsgd_build_warps(const double* K_ref, const double* K, const double*
             double Hm[9], G[9];
             mat3_mul(Ki, A, Hm);
             mat3_mul(Hm, Kr_inv, Hm);
-            if (!mat3_inv(Hm, G) || !(std::fabs(G[8]) > 0.0)) {
+            // a singular map is refused in either direction
+            const bool ok = mat3_inv(Hm, G);
+            if (!to_reference) memcpy(G, Hm, sizeof G);
+            if (!ok || !(std::fabs(G[8]) > 0.0)) {
                 delete[] tmp;
-                return fail(HSGD_E_ARG, "hsgd_build_warps: view %d plane %d map is singular", i, z);
+                return fail(HSGD_E_ARG, "%s: view %d plane %d map is singular", fn, i, z);
             }
             // normalise by |G[8]|: positions unchanged, the sign of the homogeneous
             // coordinate (in front of / behind the view) kept
@@ -279,6 +285,18 @@ hsgd_status hsgd_build_warps(const double* K_ref, const double* K, const double*
     memcpy(out, tmp, sizeof(hsgd_warp) * (size_t)N * D);
     delete[] tmp;
     return HSGD_OK;
+}
+
+hsgd_status hsgd_build_warps(const double* K_ref, const double* K, const double* R,
+                             const double* t, const double* depth, int32_t N, int32_t D,
+                             hsgd_warp* out) {
+    return build_maps(K_ref, K, R, t, depth, N, D, out, true, "hsgd_build_warps");
+}
+
+hsgd_status hsgd_build_psv_warps(const double* K_ref, const double* K, const double* R,
+                                 const double* t, const double* depth, int32_t N, int32_t D,
+                                 hsgd_warp* out) {
+    return build_maps(K_ref, K, R, t, depth, N, D, out, false, "hsgd_build_psv_warps");
 }
 
 int32_t hsgd_warps_shift_only(const hsgd_warp* warps, int32_t n) {

@@ -1248,6 +1248,138 @@ __global__ __launch_bounds__(256) void k_downsample(const float* __restrict__ im
     downsample_pixel(img, H, W, out, blockIdx.y, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// ------------------------------------------------------------------------------------
+// plane-sweep volume and its pyramid (Sec. 3.2, Hierarchical PSV Construction): a
+// workgroup samples one 64 x 16 reference tile of one (view, plane) from the source image
+// (4 consecutive pixels of a row per thread), stores it, then reduces it 2x2 level by level
+// in LDS and stores each level from there: no level is read back from memory.
+// ------------------------------------------------------------------------------------
+constexpr int kPsvTW = 64, kPsvTH = 16;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct PsvOut {
+    float* p[kPsvMaxL];
+};
+
+// RGB pixel x of a source row through the row's buffer resource: 0 outside the row (the
+// zero padding; negative x wraps to an offset past the end).
+__device__ __forceinline__ float3 rgb_at(__amdgpu_buffer_rsrc_t r, int x) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, x * 12, 0, 0);
+    return make_float3(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]));
+}
+
+__device__ __forceinline__ float3 bilerp(float w00, float w10, float w01, float w11, float3 a, float3 b,
+                                         float3 c, float3 d) {
+    return make_float3(w00 * a.x + w10 * b.x + w01 * c.x + w11 * d.x,
+                       w00 * a.y + w10 * b.y + w01 * c.y + w11 * d.y,
+                       w00 * a.z + w10 * b.z + w01 * c.z + w11 * d.z);
+}
+
+template <bool SHIFT>
+__global__ __launch_bounds__(256) void k_plane_sweep(const float* __restrict__ img,
+                                                     const hsgd_warp* __restrict__ warps, int D, int H, int W,
+                                                     int L, PsvOut out, int ntx, int nty) {
+    // levels 0.. of the tile, packed one after another: 3 * (1024 + 256 + 64 + 16 + 4) floats
+    __shared__ __align__(16) float s_lv[3 * (1024 + 256 + 64 + 16 + 4)];
+    // block -> (view, tile row, tile column, plane), the plane fastest so that the planes of
+    // one tile (the same source rows, shifted) run together; XCD-contiguous chunks
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    const int z = b % D;
+    const int tile = b / D;
+    const int tx = tile % ntx, ty = (tile / ntx) % nty, i = tile / (ntx * nty);
+    const int iz = i * D + z;
+    const hsgd_warp& wp = warps[iz];
+    const int t = threadIdx.x, gx = t & 15, ly = t >> 4;
+    const int x = tx * kPsvTW + 4 * gx, y = ty * kPsvTH + ly;
+    const float* im = img + (size_t)i * H * W * 3;
+    float3 v[4];
+    if (SHIFT) {
+        const float fx = wp.fx, fy = wp.fy, gxw = 1.0f - fx, gyw = 1.0f - fy;
+        const float w00 = gxw * gyw, w10 = fx * gyw, w01 = gxw * fy, w11 = fx * fy;
+        const int sx = x + wp.ix, sy = y + wp.iy;
+        const bool r0 = (unsigned)sy < (unsigned)H, r1 = (unsigned)(sy + 1) < (unsigned)H;
+        const auto rs0 = row_rsrc(reinterpret_cast<const char*>(im + (r0 ? (size_t)sy * W * 3 : 0)), r0 ? W * 12 : 0);
+        const auto rs1 = row_rsrc(reinterpret_cast<const char*>(im + (r1 ? (size_t)(sy + 1) * W * 3 : 0)),
+                                  r1 ? W * 12 : 0);
+        float3 a[5], c[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            a[j] = rgb_at(rs0, sx + j);
+            c[j] = rgb_at(rs1, sx + j);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = bilerp(w00, w10, w01, w11, a[j], a[j + 1], c[j], c[j + 1]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const Taps tp = make_taps(wp, x + j, y, H, W);
+            const float* p00 = im + 3 * tp.i00;
+            const float* p10 = im + 3 * tp.i10;
+            const float* p01 = im + 3 * tp.i01;
+            const float* p11 = im + 3 * tp.i11;
+            v[j] = bilerp(tp.w00, tp.w10, tp.w01, tp.w11, make_float3(p00[0], p00[1], p00[2]),
+                          make_float3(p10[0], p10[1], p10[2]), make_float3(p01[0], p01[1], p01[2]),
+                          make_float3(p11[0], p11[1], p11[2]));
+        }
+    }
+    // level 0
+    if (out.p[0] && y < H) {
+        float* o = out.p[0] + (((size_t)iz * H + y) * W + x) * 3;
+        if ((W & 3) == 0 && x < W) {                        // 16-byte aligned, 4 pixels in the row
+            f32x4* o4 = reinterpret_cast<f32x4*>(o);
+            __builtin_nontemporal_store(f32x4{v[0].x, v[0].y, v[0].z, v[1].x}, o4);
+            __builtin_nontemporal_store(f32x4{v[1].y, v[1].z, v[2].x, v[2].y}, o4 + 1);
+            __builtin_nontemporal_store(f32x4{v[2].z, v[3].x, v[3].y, v[3].z}, o4 + 2);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (x + j < W) {
+                    __builtin_nontemporal_store(v[j].x, o + 3 * j);
+                    __builtin_nontemporal_store(v[j].y, o + 3 * j + 1);
+                    __builtin_nontemporal_store(v[j].z, o + 3 * j + 2);
+                }
+        }
+    }
+    if (L == 1) return;
+    // the pyramid: level l of the tile is (16 >> l) x (64 >> l) pixels, packed after level
+    // l - 1 in s_lv; H and W are multiples of 2^(L-1), so every stored coarse pixel has its
+    // whole 2x2 block inside the image
+    {
+        float4* s4 = reinterpret_cast<float4*>(s_lv + (ly * kPsvTW + 4 * gx) * 3);
+        s4[0] = make_float4(v[0].x, v[0].y, v[0].z, v[1].x);
+        s4[1] = make_float4(v[1].y, v[1].z, v[2].x, v[2].y);
+        s4[2] = make_float4(v[2].z, v[3].x, v[3].y, v[3].z);
+    }
+    const int vh0 = min(kPsvTH, H - ty * kPsvTH), vw0 = min(kPsvTW, W - tx * kPsvTW);
+    int src_off = 0, dst_off = kPsvTH * kPsvTW * 3;
+    for (int l = 1; l < L; ++l) {
+        __syncthreads();
+        const int th = kPsvTH >> l, tw = kPsvTW >> l;
+        const int vh = vh0 >> l, vw = vw0 >> l;
+        const int Hl = H >> l, Wl = W >> l;
+        for (int e = t; e < th * tw; e += 256) {
+            const int ey = e / tw, ex = e - ey * tw;
+            const float* s = s_lv + src_off + ((2 * ey) * (2 * tw) + 2 * ex) * 3;
+            const float* s2 = s + 2 * tw * 3;
+            float r[3];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) r[ch] = ((s[ch] + s[3 + ch]) + (s2[ch] + s2[3 + ch])) * 0.25f;
+            float* d = s_lv + dst_off + e * 3;
+            d[0] = r[0];
+            d[1] = r[1];
+            d[2] = r[2];
+            if (out.p[l] && ey < vh && ex < vw) {
+                float* o = out.p[l] + (((size_t)iz * Hl + ty * th + ey) * Wl + tx * tw + ex) * 3;
+                __builtin_nontemporal_store(r[0], o);
+                __builtin_nontemporal_store(r[1], o + 1);
+                __builtin_nontemporal_store(r[2], o + 2);
+            }
+        }
+        src_off = dst_off;
+        dst_off += th * tw * 3;
+    }
+}
+
 template <int SDT, int DDT>
 __global__ __launch_bounds__(256) void k_convert(const void* __restrict__ src, void* __restrict__ dst,
                                                  int64_t n) {
@@ -1509,6 +1641,21 @@ int launch_downsample(const float* img, int N, int H, int W, float* out, hipStre
     const dim3 grid((unsigned)ceil_div((int64_t)(H / 2) * (W / 2), 256), (unsigned)N);
     ProfScope ps(HSGD_K_DOWNSAMPLE, s);
     hipLaunchKernelGGL(k_downsample, grid, dim3(256), 0, s, img, H, W, out);
+    return (int)hipGetLastError();
+}
+
+int launch_plane_sweep(const hsgd_views& src, int D, int L, float* const* out, hipStream_t s) {
+    const int ntx = (int)ceil_div(src.W, kPsvTW), nty = (int)ceil_div(src.H, kPsvTH);
+    const int64_t nb = (int64_t)ntx * nty * src.N * D;
+    PsvOut o{};
+    for (int l = 0; l < L; ++l) o.p[l] = out[l];
+    ProfScope ps(HSGD_K_PSV, s);
+    if (src.flags & HSGD_VIEWS_SHIFT_ONLY)
+        hipLaunchKernelGGL(k_plane_sweep<true>, dim3((unsigned)nb), dim3(256), 0, s, src.images, src.warps, D,
+                           src.H, src.W, L, o, ntx, nty);
+    else
+        hipLaunchKernelGGL(k_plane_sweep<false>, dim3((unsigned)nb), dim3(256), 0, s, src.images, src.warps, D,
+                           src.H, src.W, L, o, ntx, nty);
     return (int)hipGetLastError();
 }
 

@@ -51,7 +51,7 @@ hipEvent_t take_event(Profiler& p) {
 const char* kind_name(int k) {
     static const char* names[kNumKinds] = {"k_select", "k_scan", "k_compact", "k_render",
                                            "k_grad", "k_update", "k_fill_zero", "k_reduce",
-                                           "k_upsample", "k_downsample", "k_convert"};
+                                           "k_upsample", "k_downsample", "k_convert", "k_plane_sweep"};
     return (k >= 0 && k < kNumKinds) ? names[k] : "";
 }
 

@@ -90,6 +90,7 @@ _SIGS = {
     "hsgd_last_error": (ctypes.c_char_p, []),
     "hsgd_version": (_I, []),
     "hsgd_build_warps": (_I, [_P, _P, _P, _P, _P, _I, _I, _P]),
+    "hsgd_build_psv_warps": (_I, [_P, _P, _P, _P, _P, _I, _I, _P]),
     "hsgd_level_intrinsics": (_I, [_P, _I, _I, _I, _I, _P]),
     "hsgd_warps_shift_only": (_I, [_P, _I]),
     "hsgd_workspace_bytes": (ctypes.c_size_t, [_I, _I, _I, _I, _I, _I, _I]),
@@ -100,6 +101,7 @@ _SIGS = {
                             _P, ctypes.c_size_t, _P]),
     "hsgd_upsample2x": (_I, [ctypes.POINTER(Mpi), ctypes.POINTER(Mpi), _P]),
     "hsgd_downsample2x": (_I, [_P, _I, _I, _I, _P, _P]),
+    "hsgd_plane_sweep": (_I, [ctypes.POINTER(Views), _I, _I, _P, _P]),
     "hsgd_refine": (_I, [ctypes.POINTER(Mpi), ctypes.POINTER(Views), _I, _P, SelectParams, _F, _F, _F,
                          _P, _P, ctypes.c_size_t, _P]),
     "hsgd_convert": (_I, [_P, _I, _P, _I, ctypes.c_size_t, _P]),
@@ -122,8 +124,8 @@ _SIGS = {
 HSGD_E_CAPACITY, HSGD_E_BUDGET = -4, -7
 
 K_SELECT, K_SCAN, K_COMPACT, K_RENDER, K_GRAD, K_UPDATE, K_FILL, K_REDUCE, K_UPSAMPLE, \
-    K_DOWNSAMPLE, K_CONVERT = range(11)
-K_COUNT = 11
+    K_DOWNSAMPLE, K_CONVERT, K_PSV = range(12)
+K_COUNT = 12
 
 _lib = None
 
@@ -243,6 +245,15 @@ def workspace(op: int, D: int, H: int, W: int, N: int, k: int, L: int = 1, devic
 # ---------------------------------------------------------------------------------------
 def hsgd_build_warps(K_ref, K, R, t, depths) -> np.ndarray:
     """FP64 plane maps for N views x D planes; returns a uint8 array [N][D][64] (hsgd_warp)."""
+    return _build_maps("hsgd_build_warps", K_ref, K, R, t, depths)
+
+
+def hsgd_build_psv_warps(K_ref, K, R, t, depths) -> np.ndarray:
+    """FP64 plane-sweep maps (reference pixel on plane z -> source view i), [N][D][64]."""
+    return _build_maps("hsgd_build_psv_warps", K_ref, K, R, t, depths)
+
+
+def _build_maps(fn, K_ref, K, R, t, depths) -> np.ndarray:
     K_ref = np.ascontiguousarray(K_ref, dtype=np.float64).reshape(9)
     K = np.ascontiguousarray(K, dtype=np.float64).reshape(-1, 9)
     R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1, 9)
@@ -252,8 +263,8 @@ def hsgd_build_warps(K_ref, K, R, t, depths) -> np.ndarray:
     if R.shape[0] != N or t.shape[0] != N:
         raise ValueError("K, R, t must have one entry per view")
     out = (Warp * (N * D))()
-    _check(lib().hsgd_build_warps(K_ref.ctypes.data, K.ctypes.data, R.ctypes.data, t.ctypes.data,
-                                  depths.ctypes.data, N, D, ctypes.addressof(out)))
+    _check(getattr(lib(), fn)(K_ref.ctypes.data, K.ctypes.data, R.ctypes.data, t.ctypes.data,
+                              depths.ctypes.data, N, D, ctypes.addressof(out)))
     return np.frombuffer(bytes(out), dtype=np.uint8).reshape(N, D, 64).copy()
 
 
@@ -278,6 +289,11 @@ def level_warps(K_ref, K, R, t, depths, W: int, H: int, Wl: int, Hl: int, device
     K_l = np.stack([hsgd_level_intrinsics(k, W, H, Wl, Hl) for k in np.asarray(K).reshape(-1, 3, 3)])
     raw = hsgd_build_warps(Kr_l, K_l, R, t, depths)
     return WarpTable(raw, device)
+
+
+def psv_warps(K_ref, K, R, t, depths, device="cuda") -> WarpTable:
+    """Plane-sweep map table (N x D records) on the device for the rig's own resolution."""
+    return WarpTable(hsgd_build_psv_warps(K_ref, K, R, t, depths), device)
 
 
 # ---------------------------------------------------------------------------------------
@@ -366,6 +382,42 @@ def hsgd_downsample2x(images: torch.Tensor, stream=None) -> torch.Tensor:
     out = torch.empty((N, H // 2, W // 2, 3), dtype=torch.float32, device=images.device)
     _check(lib().hsgd_downsample2x(_ptr(images), N, H, W, _ptr(out), _stream(stream)))
     return out
+
+
+def hsgd_plane_sweep(images: torch.Tensor, warps, D: int, L: int = 1, store=None, out=None,
+                     stream=None) -> list:
+    """Hierarchical plane-sweep volume of source images [N][H][W][3] (FP32, device) through a
+    psv_warps table: a list of L tensors [N][D][H>>l][W>>l][3] FP32, level 0 first. store:
+    per-level booleans (levels not stored are None in the result); out: preallocated
+    tensors (or None entries) in place of fresh ones."""
+    _dev(images, "images")
+    _f32(images, "images")
+    if images.dim() != 4 or images.shape[-1] != 3:
+        raise ValueError("images must be [N][H][W][3]")
+    N, H, W, _ = images.shape
+    if isinstance(warps, WarpTable):
+        if (warps.N, warps.D) != (N, D):
+            raise ValueError(f"warp table is {warps.N} x {warps.D}, expected {N} x {D}")
+    elif warps.numel() < N * D * 64:
+        raise ValueError("warp table holds fewer than N * D records")
+    v = views_desc(warps, N, H, W, images)
+    store = [True] * L if store is None else list(store)
+    if len(store) != L:
+        raise ValueError("store needs one entry per level")
+    res = []
+    for l in range(L):
+        t = None
+        if out is not None and out[l] is not None:
+            t = out[l]
+            if tuple(t.shape) != (N, D, H >> l, W >> l, 3) or t.dtype != torch.float32:
+                raise ValueError(f"out[{l}] must be float32 [{N}][{D}][{H >> l}][{W >> l}][3]")
+            _dev(t, f"out[{l}]")
+        elif store[l]:
+            t = torch.empty((N, D, H >> l, W >> l, 3), dtype=torch.float32, device=images.device)
+        res.append(t)
+    ptrs = (ctypes.c_void_p * L)(*[_ptr(t) for t in res])
+    _check(lib().hsgd_plane_sweep(ctypes.byref(v), D, L, ctypes.addressof(ptrs), _stream(stream)))
+    return res
 
 
 def hsgd_convert(src: torch.Tensor, dtype: torch.dtype, stream=None) -> torch.Tensor:

@@ -70,6 +70,52 @@ def test_general_warps_match_oracle_maps():
         np.testing.assert_allclose(np.array(w.G).reshape(3, 3), g, rtol=1e-6, atol=1e-6)
 
 
+def test_psv_warps_are_the_plane_homographies():
+    # the plane-sweep records hold H_i^{-1}(d_z) itself (reference pixel -> source view)
+    rg = rig(5, 3, 6, 80, 60, 70.0, 0.1, general=True)
+    raw = hsgd.hsgd_build_psv_warps(rg["K_ref"], rg["K"], rg["R"], rg["t"], rg["depths"])
+    for idx, w in enumerate(hsgd.warp_records(raw)):
+        assert w.is_shift == 0
+        i, z = divmod(idx, 6)
+        h = O.plane_homography(rg["K_ref"], rg["K"][i], rg["R"][i], rg["t"][i], rg["depths"][z])
+        np.testing.assert_allclose(np.array(w.G).reshape(3, 3), h / abs(h[2, 2]), rtol=1e-6, atol=1e-6)
+
+
+def test_psv_translation_split_is_exact():
+    rg = rig(3, 4, 32, 512, 384, 400.0, 0.1)
+    recs = hsgd.warp_records(hsgd.hsgd_build_psv_warps(rg["K_ref"], rg["K"], rg["R"], rg["t"], rg["depths"]))
+    for i in range(4):
+        for z in range(32):
+            w = recs[i * 32 + z]
+            s = 400.0 * rg["t"][i, :2] / rg["depths"][z]           # reference -> source: + f t / d
+            assert w.is_shift == 1
+            assert 0.0 <= w.fx < 1.0 and 0.0 <= w.fy < 1.0
+            assert abs(w.ix + float(w.fx) - s[0]) < 1e-6
+            assert abs(w.iy + float(w.fy) - s[1]) < 1e-6
+
+
+def test_plane_sweep_validation():
+    L = hsgd.lib()
+    by = ctypes.byref
+    three = (ctypes.c_void_p * 3)(FAKE, None, FAKE)
+    none3 = (ctypes.c_void_p * 3)(None, None, None)
+    odd = (ctypes.c_void_p * 1)(FAKE + 4)
+    ps = L.hsgd_plane_sweep
+    assert ps(None, 8, 3, three, None) == -1
+    assert ps(by(_views()), 8, 3, None, None) == -1
+    assert ps(by(_views(images=None)), 8, 3, three, None) == -1
+    assert ps(by(_views(warps=None)), 8, 3, three, None) == -1
+    assert ps(by(_views(N=0)), 8, 3, three, None) == -2
+    assert ps(by(_views()), 0, 3, three, None) == -2
+    assert ps(by(_views()), 65, 3, three, None) == -2
+    assert ps(by(_views()), 8, 0, three, None) == -2
+    assert ps(by(_views()), 8, 6, three, None) == -2
+    assert ps(by(_views(H=18)), 8, 3, three, None) == -2          # 18 is not a multiple of 4
+    assert ps(by(_views()), 8, 3, none3, None) == -1              # nothing to store
+    assert ps(by(_views()), 8, 1, odd, None) == -1                # misaligned output
+    assert "aligned" in L.hsgd_last_error().decode()
+
+
 def test_level_intrinsics_match_oracle():
     K = np.array([[400.0, 0.3, 250.0], [0, 380.0, 190.0], [0, 0, 1]])
     np.testing.assert_allclose(hsgd.hsgd_level_intrinsics(K, 512, 384, 128, 96),
