@@ -337,6 +337,23 @@ def views_cpu_baseline():
             "sample": f"3 of the 18 novel views of a {sc.W}x{sc.H}x{sc.D} MPI (FP64 NumPy, {dt:.1f} s)"}
 
 
+def calibrate_copy(args, out):
+    """--calibrate-copy N: N launches of the library's FP32 copy over 256 MiB, whose memory
+    counters scale those of the measured kernel to bytes."""
+    if not args.calibrate_copy:
+        return
+    import torch
+
+    from paper_2307_03017_amd import hsgd
+
+    n = 64 * 1024 * 1024   # floats = 256 MiB
+    a = torch.empty(n, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    for _ in range(args.calibrate_copy):
+        hsgd.hsgd_convert(a, torch.float32)
+    torch.cuda.synchronize()
+    out["calibration_copy_bytes"] = 2 * 4 * n
+
+
 PSV_RIGS = {"psv": ("c2", 3), "psv5": ("c5", 4)}
 
 
@@ -420,6 +437,7 @@ def psv_bench(args):
             "alg_bytes_per_launch": alg_bytes,
         },
     }
+    calibrate_copy(args, res)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = psv_cpu_baseline(cfg, L)
     print(json.dumps(res), flush=True)
@@ -591,14 +609,7 @@ def main():
     out["path_roofline"]["frac_at_p50"] = (out["path_roofline"]["alg_bytes_per_refine"]
                                            / (out["p50_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS)
 
-    if args.calibrate_copy:
-        n = 64 * 1024 * 1024   # floats = 256 MiB
-        a = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
-        for _ in range(args.calibrate_copy):
-            hsgd.hsgd_convert(a, torch.float32)
-        torch.cuda.synchronize()
-        out["calibration_copy_bytes"] = 2 * 4 * n
-
+    calibrate_copy(args, out)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

@@ -119,8 +119,9 @@ hsgd_status hsgd_plane_sweep(const hsgd_views* src, int32_t D, int32_t L, float*
     const int s = 1 << (L - 1);
     if (src->H < 1 || src->W < 1 || src->H % s || src->W % s)
         return fail(HSGD_E_SHAPE, "%s: %dx%d is not a positive multiple of 2^(L-1) = %d", fn, src->W, src->H, s);
-    if ((int64_t)src->N * D * ((src->W + 63) / 64) * ((src->H + 15) / 16) > INT32_MAX)
-        return fail(HSGD_E_SHAPE, "%s: volume too large for one launch", fn);
+    if ((int64_t)src->N * D * ((src->W + 63) / 64) * ((src->H + 15) / 16) > INT32_MAX ||
+        (int64_t)src->H * src->W * 12 > INT32_MAX)
+        return fail(HSGD_E_SHAPE, "%s: volume or image too large for one launch", fn);
     bool any = false;
     for (int l = 0; l < L; ++l) {
         if ((uintptr_t)out[l] % 16) return fail(HSGD_E_ARG, "%s: out[%d] is not 16-byte aligned", fn, l);
