@@ -405,6 +405,13 @@ def psv_bench(args):
     alg_bytes = sc.N * HW * 12 + wr                 # images read once, every level written once
     t_launch = ms_k * 1e-3 / max(n_k, 1)
     gbs = alg_bytes / t_launch / 1e9
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", f"k_plane_sweep_traffic_{args.workload}_fp32.json")
+    if os.path.exists(tf):
+        with open(tf) as fh:
+            rec = json.load(fh)
+        if rec.get("kernel_source_hash") == kernel_source_hash():
+            traffic = rec.get("hbm_bytes_per_launch")
     res = {
         "metric": f"plane-sweep volume samples/s ({sc.W}x{sc.H}, {sc.D} planes, {sc.N} views, {L} levels)",
         "value": samples * steps / wall,
@@ -431,7 +438,7 @@ def psv_bench(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": gbs / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
             "launches": n_k,
             "avg_launch_us": t_launch * 1e6,
             "alg_bytes_per_launch": alg_bytes,
