@@ -57,12 +57,10 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("hsgd_kernels.hip",):
-        with open(os.path.join(ROOT, "paper_2307_03017_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+def kernel_source_hash(kernel="k_grad_shift"):
+    from paper_2307_03017_amd.profiling import kernel_source_hash as h
+
+    return h(kernel)
 
 
 def grad_launch_bytes(D, shapes, iters, N, k, s):
@@ -410,7 +408,7 @@ def psv_bench(args):
     if os.path.exists(tf):
         with open(tf) as fh:
             rec = json.load(fh)
-        if rec.get("kernel_source_hash") == kernel_source_hash():
+        if rec.get("kernel_source_hash") == kernel_source_hash("k_plane_sweep"):
             traffic = rec.get("hbm_bytes_per_launch")
     res = {
         "metric": f"plane-sweep volume samples/s ({sc.W}x{sc.H}, {sc.D} planes, {sc.N} views, {L} levels)",

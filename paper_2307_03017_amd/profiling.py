@@ -24,10 +24,18 @@ from collections import defaultdict
 _PKG = os.path.dirname(os.path.abspath(__file__))
 
 
-def kernel_source_hash() -> str:
+# the sources a kernel is compiled from (a recorded traffic figure holds while they are unchanged)
+KERNEL_SOURCES = {
+    "k_plane_sweep": ("hsgd_psv.hip", "hsgd_device.h", "hsgd_internal.h"),
+}
+DEFAULT_SOURCES = ("hsgd_kernels.hip", "hsgd_device.h", "hsgd_internal.h")
+
+
+def kernel_source_hash(kernel: str = "k_grad_shift") -> str:
     h = hashlib.sha256()
-    with open(os.path.join(_PKG, "csrc", "hsgd_kernels.hip"), "rb") as fh:
-        h.update(fh.read())
+    for f in KERNEL_SOURCES.get(kernel, DEFAULT_SOURCES):
+        with open(os.path.join(_PKG, "csrc", f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -110,7 +118,7 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, copy_k
         launches.append(dict(kernel=key[0], grid=key[1], read_bytes=rb, write_bytes=wb))
     mean = sum(l["read_bytes"] + l["write_bytes"] for l in launches) / max(len(launches), 1)
     return dict(kernel=kernel, fetch_factor=f_factor, write_factor=w_factor, launches=launches,
-                hbm_bytes_per_launch=mean, kernel_source_hash=kernel_source_hash())
+                hbm_bytes_per_launch=mean, kernel_source_hash=kernel_source_hash(kernel))
 
 
 def traffic_md(t, cmd: str) -> str:
