@@ -335,6 +335,19 @@ def views_cpu_baseline():
             "sample": f"3 of the 18 novel views of a {sc.W}x{sc.H}x{sc.D} MPI (FP64 NumPy, {dt:.1f} s)"}
 
 
+def l2_hit_rate(kernel, workload):
+    """The kernel's L2 hit rate from the committed counter summary of this workload, while
+    the kernel's sources are unchanged since it was taken (else None)."""
+    f = os.path.join(ROOT, "profiles", f"l2_hit_{workload}.json")
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_hash", {}).get(kernel) != kernel_source_hash(kernel):
+        return None
+    return rec.get("hit_rate", {}).get(kernel)
+
+
 def calibrate_copy(args, out):
     """--calibrate-copy N: N launches of the library's FP32 copy over 256 MiB, whose memory
     counters scale those of the measured kernel to bytes."""
@@ -437,6 +450,7 @@ def psv_bench(args):
             "unit": "GB/s",
             "frac": gbs / HBM_PEAK_GBS,
             "traffic": traffic,
+            "l2_hit": l2_hit_rate("k_plane_sweep", args.workload),
             "launches": n_k,
             "avg_launch_us": t_launch * 1e6,
             "alg_bytes_per_launch": alg_bytes,
@@ -598,6 +612,7 @@ def main():
             "frac": ((achieved_tf / FP32_VECTOR_PEAK_TFLOPS) if alu_bound else
                      (achieved_gbs / HBM_PEAK_GBS)) if ms_grad > 0 else None,
             "traffic": traffic,
+            "l2_hit": l2_hit_rate("k_grad_shift", f"{args.workload}_{args.dtype}"),
             "launches": n_grad,
             "avg_launch_us": ms_grad * 1e3 / max(n_grad, 1),
             "alg_bytes_per_launch": gbytes / glaunch,

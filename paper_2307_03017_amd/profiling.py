@@ -135,6 +135,42 @@ def traffic_md(t, cmd: str) -> str:
     return "\n".join(out) + "\n"
 
 
+def l2(csv_path: str):
+    """L2 (TCC) hit rate per kernel from a TCC_HIT_sum / TCC_MISS_sum counter run: hits over
+    requests, summed over every dispatch of the kernel (all template instances of one
+    kernel name pooled, grid sizes kept apart)."""
+    hits = _counter_rows(csv_path, "TCC_HIT_sum")
+    miss = _counter_rows(csv_path, "TCC_MISS_sum")
+    agg = defaultdict(lambda: [0.0, 0.0, 0])
+    for n, g, v in hits:
+        agg[(n, g)][0] += v
+        agg[(n, g)][2] += 1
+    for n, g, v in miss:
+        agg[(n, g)][1] += v
+    rows = []
+    for (n, g), (h, m, c) in sorted(agg.items()):
+        rows.append(dict(kernel=n, grid=g, dispatches=c, hits=h, misses=m, hit_rate=h / (h + m) if h + m else None))
+    by_kernel = defaultdict(lambda: [0.0, 0.0])
+    for r in rows:
+        base = r["kernel"].split("<")[0]
+        by_kernel[base][0] += r["hits"]
+        by_kernel[base][1] += r["misses"]
+    return dict(rows=rows, hit_rate={k: h / (h + m) for k, (h, m) in by_kernel.items() if h + m},
+                kernel_source_hash={k: kernel_source_hash(k) for k in by_kernel})
+
+
+def l2_md(t, cmd: str) -> str:
+    out = ["# L2 hit rate per kernel", "", "Command:", "", "```", cmd, "```", "",
+           "TCC_HIT_sum / (TCC_HIT_sum + TCC_MISS_sum) over the dispatches of each kernel "
+           "(summed over every L2 channel of the 8 XCDs).", "",
+           "| kernel | grid | dispatches | hit rate |", "|---|---:|---:|---:|"]
+    for r in t["rows"]:
+        hr = "—" if r["hit_rate"] is None else f"{100 * r['hit_rate']:.1f}%"
+        out.append(f"| `{r['kernel']}` | {r['grid']} | {r['dispatches']} | {hr} |")
+    out += ["", "Per kernel (all launches): " + ", ".join(f"`{k}` {100 * v:.1f}%" for k, v in sorted(t["hit_rate"].items()))]
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd_name", required=True)
@@ -150,8 +186,21 @@ def main(argv=None):
     b.add_argument("--cmd", default="")
     b.add_argument("--json")
     b.add_argument("--md")
+    c = sub.add_parser("l2")
+    c.add_argument("csv")
+    c.add_argument("--cmd", default="")
+    c.add_argument("--json")
+    c.add_argument("--md")
     args = ap.parse_args(argv)
-    if args.cmd_name == "stats":
+    if args.cmd_name == "l2":
+        t = l2(args.csv)
+        if args.json:
+            json.dump(t, open(args.json, "w"), indent=1)
+        md = l2_md(t, args.cmd)
+        if args.md:
+            open(args.md, "w").write(md)
+        print(md)
+    elif args.cmd_name == "stats":
         md = stats_md(read_stats(args.csv), args.cmd)
         if args.md:
             open(args.md, "w").write(md)
