@@ -625,6 +625,13 @@ def main():
         "path_roofline": {
             "alg_bytes_per_refine": refine_alg_bytes(sc.D, plan.shapes, sc.iters, sc.N, sc.k, s_bytes),
         },
+        # the paper's only speed figures: whole MPI generation (plane sweep, 3D CNNs, learned
+        # iterations) on other hardware (Table 1 and the ablation of Sec. 4); context only
+        "paper_context": {
+            "mpi_generation_s": 0.026, "fps": 37.04, "hardware": "RTX 3090, TensorRT",
+            "workload": "378x512, 40 planes, 3 views, k=5, 3 learned iterations incl. 3D CNNs",
+            "dense_voxels_per_s_finest_level": 378 * 512 * 40 * 37.04,
+        },
     }
     out["path_roofline"]["frac_at_p50"] = (out["path_roofline"]["alg_bytes_per_refine"]
                                            / (out["p50_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS)
