@@ -386,11 +386,13 @@ def psv_bench(args):
     images, _ = hsgd.hsgd_render(gt, views, sc.N)
     del gt
     table = hsgd.psv_warps(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths, dev)
-    out = hsgd.hsgd_plane_sweep(images, table, sc.D, L)
+    odt = torch.bfloat16 if args.dtype == "bf16" else torch.float32
+    vbytes = 6 if args.dtype == "bf16" else 12
+    out = hsgd.hsgd_plane_sweep(images, table, sc.D, L, dtype=odt)
     stream = torch.cuda.current_stream()
 
     def step():
-        hsgd.hsgd_plane_sweep(images, table, sc.D, L, out=out)
+        hsgd.hsgd_plane_sweep(images, table, sc.D, L, out=out, dtype=odt)
 
     for _ in range(args.warmup):
         step()
@@ -412,12 +414,12 @@ def psv_bench(args):
     n_k, ms_k = kt.result[hsgd.K_PSV]
     HW = sc.H * sc.W
     samples = sc.N * sc.D * HW
-    wr = sum(samples // 4 ** l * 12 for l in range(L))
+    wr = sum(samples // 4 ** l * vbytes for l in range(L))
     alg_bytes = sc.N * HW * 12 + wr                 # images read once, every level written once
     t_launch = ms_k * 1e-3 / max(n_k, 1)
     gbs = alg_bytes / t_launch / 1e9
     traffic = None
-    tf = os.path.join(ROOT, "profiles", f"k_plane_sweep_traffic_{args.workload}_fp32.json")
+    tf = os.path.join(ROOT, "profiles", f"k_plane_sweep_traffic_{args.workload}_{args.dtype}.json")
     if os.path.exists(tf):
         with open(tf) as fh:
             rec = json.load(fh)
@@ -434,11 +436,11 @@ def psv_bench(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.dtype == "fp32" else "f32/bf16-storage",
         "data": "synthetic",
         "config": {"workload": (f"hsgd_plane_sweep of {sc.N} {sc.W}x{sc.H} source images onto {sc.D} "
                                 f"planes, {L} levels {'->'.join(f'{sc.W >> l}x{sc.H >> l}' for l in range(L))}, "
-                                f"translation rig"),
+                                f"translation rig, {args.dtype} output"),
                    "bytes_written_per_step": wr},
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
@@ -500,6 +502,7 @@ def main():
         views_bench(args)
         return
     if args.workload in PSV_RIGS:
+        args.dtype = args.dtype or "fp32"
         psv_bench(args)
         return
 

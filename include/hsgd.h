@@ -251,14 +251,17 @@ hsgd_status hsgd_downsample2x(const float* images, int32_t N, int32_t H, int32_t
  *         records from hsgd_build_psv_warps for an H x W reference camera; flags
  *         HSGD_VIEWS_SHIFT_ONLY as for the other calls (translation path).
  *  D      planes, 1..64; L levels, 1..5; H and W multiples of 2^(L-1).
+ *  out_dtype  HSGD_FP32 or HSGD_BF16 (every level computed in FP32 from the FP32 level
+ *         above, rounded to nearest even once, on store).
  *  out    host array of L device pointers, 16-byte aligned: out[l] receives
- *         [N][D][H>>l][W>>l][3] FP32; a NULL entry skips storing that level (at least one
- *         must be set). Caller owns all buffers; no workspace.
+ *         [N][D][H>>l][W>>l][3] of out_dtype; a NULL entry skips storing that level (at
+ *         least one must be set). Caller owns all buffers; no workspace.
  * Errors: HSGD_E_ARG (NULL images/warps/out, every out[l] NULL, misaligned out),
- *         HSGD_E_SHAPE (N, D, L, H, W out of range), HSGD_E_HIP (launch failure).
+ *         HSGD_E_SHAPE (N, D, L, H, W out of range), HSGD_E_DTYPE (unknown out_dtype),
+ *         HSGD_E_HIP (launch failure).
  */
-hsgd_status hsgd_plane_sweep(const hsgd_views* src, int32_t D, int32_t L, float* const* out,
-                             hipStream_t stream);
+hsgd_status hsgd_plane_sweep(const hsgd_views* src, int32_t D, int32_t L, int32_t out_dtype,
+                             void* const* out, hipStream_t stream);
 
 /*
  * hsgd_refine -- the whole coarse-to-fine HSGD refinement (Sec. 3.3; Fig. pipeline).

@@ -107,7 +107,7 @@ hsgd_status hsgd_downsample2x(const float* images, int32_t N, int32_t H, int32_t
     return hip_status(launch_downsample(images, N, H, W, out, stream), fn);
 }
 
-hsgd_status hsgd_plane_sweep(const hsgd_views* src, int32_t D, int32_t L, float* const* out,
+hsgd_status hsgd_plane_sweep(const hsgd_views* src, int32_t D, int32_t L, int32_t out_dtype, void* const* out,
                              hipStream_t stream) {
     clear_error();
     const char* fn = "hsgd_plane_sweep";
@@ -116,6 +116,7 @@ hsgd_status hsgd_plane_sweep(const hsgd_views* src, int32_t D, int32_t L, float*
     if (src->N < 1 || src->N > kMaxN || D < 1 || D > kMaxD)
         return fail(HSGD_E_SHAPE, "%s: N=%d or D=%d out of range", fn, src->N, D);
     if (L < 1 || L > kPsvMaxL) return fail(HSGD_E_SHAPE, "%s: L=%d outside [1, %d]", fn, L, kPsvMaxL);
+    if (out_dtype != HSGD_FP32 && out_dtype != HSGD_BF16) return fail(HSGD_E_DTYPE, "%s: unknown dtype %d", fn, out_dtype);
     const int s = 1 << (L - 1);
     if (src->H < 1 || src->W < 1 || src->H % s || src->W % s)
         return fail(HSGD_E_SHAPE, "%s: %dx%d is not a positive multiple of 2^(L-1) = %d", fn, src->W, src->H, s);
@@ -128,7 +129,7 @@ hsgd_status hsgd_plane_sweep(const hsgd_views* src, int32_t D, int32_t L, float*
         any = any || out[l];
     }
     if (!any) return fail(HSGD_E_ARG, "%s: every output level is NULL", fn);
-    return hip_status(launch_plane_sweep(*src, D, L, out, stream), fn);
+    return hip_status(launch_plane_sweep(*src, D, L, out_dtype, out, stream), fn);
 }
 
 hsgd_status hsgd_convert(const void* src, int32_t src_dtype, void* dst, int32_t dst_dtype,

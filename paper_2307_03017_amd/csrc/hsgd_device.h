@@ -8,6 +8,14 @@
 namespace hsgd {
 namespace {
 
+// FP32 -> BF16 bits, round to nearest even (NaN stays a quiet NaN).
+__device__ __forceinline__ uint32_t f32_to_bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
 // Raw (untyped, stride 0) buffer resource over one MPI row of n_bytes bytes: loads at
 // offsets outside [0, n_bytes) return 0, which is the zero padding of a plane outside the
 // image; n_bytes = 0 makes a whole row read as padding. Word 3 selects the 32-bit data

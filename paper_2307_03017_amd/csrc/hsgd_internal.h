@@ -119,9 +119,9 @@ int launch_upsample(const hsgd_mpi& coarse, const hsgd_mpi& fine, hipStream_t s)
 int launch_upsample_select(const hsgd_mpi& coarse, const hsgd_mpi& fine, int k, float tau, int rule, uint64_t* mask,
                            hipStream_t s);
 int launch_downsample(const float* img, int N, int H, int W, float* out, hipStream_t s);
-// plane-sweep volume levels 0..L-1 ([N][D][H>>l][W>>l][3]; out[l] NULL: not stored)
+// plane-sweep volume levels 0..L-1 ([N][D][H>>l][W>>l][3] FP32 or BF16; out[l] NULL: not stored)
 constexpr int kPsvMaxL = 5;
-int launch_plane_sweep(const hsgd_views& src, int D, int L, float* const* out, hipStream_t s);
+int launch_plane_sweep(const hsgd_views& src, int D, int L, int out_dtype, void* const* out, hipStream_t s);
 int launch_convert(const void* src, int sdt, void* dst, int ddt, size_t n, hipStream_t s);
 
 // ---- batched serving step (hsgd_batch.cpp builds the table, hsgd_kernels.hip runs it) ----

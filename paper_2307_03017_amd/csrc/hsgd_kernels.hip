@@ -22,12 +22,6 @@ namespace {
 // ------------------------------------------------------------------------------------
 // storage: FP32 float4 or BF16 (4 x 16 bit, round to nearest even on store)
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t f32_to_bf16_bits(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;  // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return u >> 16;
-}
 
 template <int DT>
 struct Vox;

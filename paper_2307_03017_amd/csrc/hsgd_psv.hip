@@ -20,21 +20,25 @@ constexpr int kPsvTW = 64, kPsvTH = 16;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct PsvOut {
-    float* p[kPsvMaxL];
+    void* p[kPsvMaxL];
 };
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
 __device__ __forceinline__ void st_stream(T v, T* p) {
     __builtin_nontemporal_store(v, p);
 }
 
-// Store the valid vh x vw pixels of a TH x TW tile, row-major in LDS, to rows of Wl pixels at
-// dst: float4 runs when every row start is 16-byte aligned (Wl % 4 == 0, then vw % 4 == 0
-// too), else one pixel per lane; consecutive lanes write consecutive addresses either way.
-template <int TH, int TW>
-__device__ __forceinline__ void psv_store_tile(const float* __restrict__ s, int vh, int vw,
-                                               float* __restrict__ dst, int Wl, int t) {
-    if ((Wl & 3) == 0) {
+// Store the valid vh x vw pixels of a TH x TW tile, row-major in LDS (FP32), to rows of Wl
+// pixels at dst (the tile's first pixel) in the output type OT. 16-byte runs when every row
+// start is 16-byte aligned (FP32: Wl % 4 == 0; BF16: Wl % 8 == 0 and 16-byte tile rows; vw
+// is then a multiple of the run's pixels too), else one pixel per lane; consecutive lanes
+// write consecutive addresses either way. BF16 rounds to nearest even.
+template <int TH, int TW, int OT>
+__device__ __forceinline__ void psv_store_tile(const float* __restrict__ s, int vh, int vw, void* __restrict__ dst,
+                                               int Wl, int t) {
+    if (OT == HSGD_FP32 && (Wl & 3) == 0) {
+        float* o = reinterpret_cast<float*>(dst);
         constexpr int RQ = TW * 3 / 4;                      // float4 per tile row
         const int vq = vw * 3 / 4;
 #pragma unroll
@@ -42,7 +46,24 @@ __device__ __forceinline__ void psv_store_tile(const float* __restrict__ s, int 
             const int e = e0 + t, r = e / RQ, c = e - r * RQ;
             if ((TH * RQ % 256 == 0 || e < TH * RQ) && r < vh && c < vq) {
                 const float4 q = reinterpret_cast<const float4*>(s)[e];
-                st_stream(f32x4{q.x, q.y, q.z, q.w}, reinterpret_cast<f32x4*>(dst + (size_t)r * Wl * 3) + c);
+                st_stream(f32x4{q.x, q.y, q.z, q.w}, reinterpret_cast<f32x4*>(o + (size_t)r * Wl * 3) + c);
+            }
+        }
+    } else if (OT == HSGD_BF16 && TW * 6 % 16 == 0 && (Wl & 7) == 0) {
+        uint16_t* o = reinterpret_cast<uint16_t*>(dst);
+        constexpr int RQ = TW * 3 / 8;                      // 8 values (16 bytes) per run
+        const int vq = vw * 3 / 8;
+#pragma unroll
+        for (int e0 = 0; e0 < TH * RQ; e0 += 256) {
+            const int e = e0 + t, r = e / RQ, c = e - r * RQ;
+            if ((TH * RQ % 256 == 0 || e < TH * RQ) && r < vh && c < vq) {
+                const float4 a = reinterpret_cast<const float4*>(s)[2 * e];
+                const float4 b = reinterpret_cast<const float4*>(s)[2 * e + 1];
+                const u32x4 q{f32_to_bf16_bits(a.x) | (f32_to_bf16_bits(a.y) << 16),
+                              f32_to_bf16_bits(a.z) | (f32_to_bf16_bits(a.w) << 16),
+                              f32_to_bf16_bits(b.x) | (f32_to_bf16_bits(b.y) << 16),
+                              f32_to_bf16_bits(b.z) | (f32_to_bf16_bits(b.w) << 16)};
+                st_stream(q, reinterpret_cast<u32x4*>(o + (size_t)r * Wl * 3) + c);
             }
         }
     } else {
@@ -50,10 +71,18 @@ __device__ __forceinline__ void psv_store_tile(const float* __restrict__ s, int 
         for (int e0 = 0; e0 < TH * TW; e0 += 256) {
             const int e = e0 + t, r = e / TW, c = e - r * TW;
             if ((TH * TW % 256 == 0 || e < TH * TW) && r < vh && c < vw) {
-                float* o = dst + ((size_t)r * Wl + c) * 3;
-                st_stream(s[3 * e], o);
-                st_stream(s[3 * e + 1], o + 1);
-                st_stream(s[3 * e + 2], o + 2);
+                const size_t at = ((size_t)r * Wl + c) * 3;
+                if (OT == HSGD_FP32) {
+                    float* o = reinterpret_cast<float*>(dst) + at;
+                    st_stream(s[3 * e], o);
+                    st_stream(s[3 * e + 1], o + 1);
+                    st_stream(s[3 * e + 2], o + 2);
+                } else {
+                    uint16_t* o = reinterpret_cast<uint16_t*>(dst) + at;
+                    st_stream((uint16_t)f32_to_bf16_bits(s[3 * e]), o);
+                    st_stream((uint16_t)f32_to_bf16_bits(s[3 * e + 1]), o + 1);
+                    st_stream((uint16_t)f32_to_bf16_bits(s[3 * e + 2]), o + 2);
+                }
             }
         }
     }
@@ -124,15 +153,18 @@ __device__ __forceinline__ void psv_sample_general(const float* __restrict__ im,
 
 // Level l of a plane's tile (TH x TW pixels at LDS offset OFF) to memory, then level l + 1
 // reduced from it into LDS (2x2 means), recursively up to level L - 1.
-template <int L, int l, int OFF>
+template <int L, int l, int OFF, int OT>
 __device__ __forceinline__ void psv_level(float* __restrict__ s_lv, const PsvOut& out, int iz, int tx, int ty,
                                           int H, int W, int vh0, int vw0, int t) {
     constexpr int TH = kPsvTH >> l, TW = kPsvTW >> l;
     __syncthreads();                                        // level l complete in LDS
     const int Hl = H >> l, Wl = W >> l;
-    if (out.p[l])
-        psv_store_tile<TH, TW>(s_lv + OFF, vh0 >> l, vw0 >> l,
-                               out.p[l] + (((size_t)iz * Hl + ty * TH) * Wl + tx * TW) * 3, Wl, t);
+    if (out.p[l]) {
+        const size_t at = (((size_t)iz * Hl + ty * TH) * Wl + tx * TW) * 3;
+        void* dst = OT == HSGD_FP32 ? (void*)(reinterpret_cast<float*>(out.p[l]) + at)
+                                    : (void*)(reinterpret_cast<uint16_t*>(out.p[l]) + at);
+        psv_store_tile<TH, TW, OT>(s_lv + OFF, vh0 >> l, vw0 >> l, dst, Wl, t);
+    }
     if constexpr (l + 1 < L) {
         constexpr int NH = TH / 2, NW = TW / 2, DST = OFF + TH * TW * 3;
 #pragma unroll
@@ -148,13 +180,13 @@ __device__ __forceinline__ void psv_level(float* __restrict__ s_lv, const PsvOut
                 d[2] = ((p0.z + p1.z) + (p2.z + p3.z)) * 0.25f;
             }
         }
-        psv_level<L, l + 1, DST>(s_lv, out, iz, tx, ty, H, W, vh0, vw0, t);
+        psv_level<L, l + 1, DST, OT>(s_lv, out, iz, tx, ty, H, W, vh0, vw0, t);
     }
 }
 
 // One plane's tile from the threads' samples v to every level in memory: level l of the
 // tile ((16 >> l) x (64 >> l) pixels) is packed after level l - 1 in s_lv.
-template <int L>
+template <int L, int OT>
 __device__ __forceinline__ void psv_tile_levels(const float3 (&v)[4], float* __restrict__ s_lv,
                                                 const PsvOut& out, int iz, int tx, int ty, int H, int W,
                                                 int vh0, int vw0, int t) {
@@ -165,13 +197,14 @@ __device__ __forceinline__ void psv_tile_levels(const float3 (&v)[4], float* __r
         s4[1] = make_float4(v[1].y, v[1].z, v[2].x, v[2].y);
         s4[2] = make_float4(v[2].z, v[3].x, v[3].y, v[3].z);
     }
-    psv_level<L, 0, 0>(s_lv, out, iz, tx, ty, H, W, vh0, vw0, t);
+    psv_level<L, 0, 0, OT>(s_lv, out, iz, tx, ty, H, W, vh0, vw0, t);
 }
 
 // A workgroup takes one 64 x 16 reference tile of one (view, plane), 4 consecutive pixels
-// of a row per thread. Blocks run plane-fastest: the workgroups resident on an XCD sweep
-// the planes of neighbouring tiles, whose source rows stay in its L2.
-template <bool SHIFT, int L>
+// of a row per thread. Blocks run tile column fastest, then plane, then tile row: the
+// workgroups resident on an XCD write whole 16-row bands of a plane (long contiguous runs
+// per image row) and sweep the planes of one band, whose source rows stay in its L2.
+template <bool SHIFT, int L, int OT>
 __global__ __launch_bounds__(256) void k_plane_sweep(const float* __restrict__ img,
                                                      const hsgd_warp* __restrict__ warps, int D, int H, int W,
                                                      PsvOut out, int ntx, int nty) {
@@ -180,9 +213,9 @@ __global__ __launch_bounds__(256) void k_plane_sweep(const float* __restrict__ i
     __shared__ __align__(16) float s_lv[3 * (1024 + 256 + 64 + 16 + 4)];
     static_assert(kPsvSrcN <= 3 * (1024 + 256 + 64 + 16 + 4), "source patch exceeds the LDS tile");
     const int b = xcd_tile(blockIdx.x, gridDim.x);
-    const int z = b % D, r = b / D;
-    const int tile = r % (ntx * nty), i = r / (ntx * nty);
-    const int tx = tile % ntx, ty = tile / ntx;
+    const int tx = b % ntx, r = b / ntx;
+    const int z = r % D, r2 = r / D;
+    const int ty = r2 % nty, i = r2 / nty;
     const int iz = i * D + z;
     const hsgd_warp& wp = warps[iz];
     const int t = threadIdx.x, gx = t & 15, ly = t >> 4;
@@ -199,21 +232,25 @@ __global__ __launch_bounds__(256) void k_plane_sweep(const float* __restrict__ i
     // valid part of the tile; H and W are multiples of 2^(L-1), so every coarse pixel of it
     // has its whole 2x2 block inside the image
     const int vh0 = min(kPsvTH, H - ty * kPsvTH), vw0 = min(kPsvTW, W - tx * kPsvTW);
-    psv_tile_levels<L>(v, s_lv, out, iz, tx, ty, H, W, vh0, vw0, t);
+    psv_tile_levels<L, OT>(v, s_lv, out, iz, tx, ty, H, W, vh0, vw0, t);
 }
 
 }  // namespace
 
-int launch_plane_sweep(const hsgd_views& src, int D, int L, float* const* out, hipStream_t s) {
+int launch_plane_sweep(const hsgd_views& src, int D, int L, int out_dtype, void* const* out, hipStream_t s) {
     const int ntx = (int)ceil_div(src.W, kPsvTW), nty = (int)ceil_div(src.H, kPsvTH);
     const int64_t nb = (int64_t)ntx * nty * src.N * D;
     PsvOut o{};
     for (int l = 0; l < L; ++l) o.p[l] = out[l];
     ProfScope ps(HSGD_K_PSV, s);
     const bool shift = (src.flags & HSGD_VIEWS_SHIFT_ONLY) != 0;
-#define HSGD_PSV_LAUNCH(SH, LV)                                                                          \
-    hipLaunchKernelGGL((k_plane_sweep<SH, LV>), dim3((unsigned)nb), dim3(256), 0, s, src.images, src.warps, D, \
-                       src.H, src.W, o, ntx, nty)
+#define HSGD_PSV_LAUNCH(SH, LV)                                                                               \
+    if (out_dtype == HSGD_FP32)                                                                               \
+        hipLaunchKernelGGL((k_plane_sweep<SH, LV, HSGD_FP32>), dim3((unsigned)nb), dim3(256), 0, s, src.images, \
+                           src.warps, D, src.H, src.W, o, ntx, nty);                                          \
+    else                                                                                                      \
+        hipLaunchKernelGGL((k_plane_sweep<SH, LV, HSGD_BF16>), dim3((unsigned)nb), dim3(256), 0, s, src.images, \
+                           src.warps, D, src.H, src.W, o, ntx, nty)
     switch (L * 2 + (shift ? 1 : 0)) {
         case 2: HSGD_PSV_LAUNCH(false, 1); break;
         case 3: HSGD_PSV_LAUNCH(true, 1); break;

@@ -101,7 +101,7 @@ _SIGS = {
                             _P, ctypes.c_size_t, _P]),
     "hsgd_upsample2x": (_I, [ctypes.POINTER(Mpi), ctypes.POINTER(Mpi), _P]),
     "hsgd_downsample2x": (_I, [_P, _I, _I, _I, _P, _P]),
-    "hsgd_plane_sweep": (_I, [ctypes.POINTER(Views), _I, _I, _P, _P]),
+    "hsgd_plane_sweep": (_I, [ctypes.POINTER(Views), _I, _I, _I, _P, _P]),
     "hsgd_refine": (_I, [ctypes.POINTER(Mpi), ctypes.POINTER(Views), _I, _P, SelectParams, _F, _F, _F,
                          _P, _P, ctypes.c_size_t, _P]),
     "hsgd_convert": (_I, [_P, _I, _P, _I, ctypes.c_size_t, _P]),
@@ -385,11 +385,14 @@ def hsgd_downsample2x(images: torch.Tensor, stream=None) -> torch.Tensor:
 
 
 def hsgd_plane_sweep(images: torch.Tensor, warps, D: int, L: int = 1, store=None, out=None,
-                     stream=None) -> list:
+                     stream=None, dtype: torch.dtype = torch.float32) -> list:
     """Hierarchical plane-sweep volume of source images [N][H][W][3] (FP32, device) through a
-    psv_warps table: a list of L tensors [N][D][H>>l][W>>l][3] FP32, level 0 first. store:
-    per-level booleans (levels not stored are None in the result); out: preallocated
-    tensors (or None entries) in place of fresh ones."""
+    psv_warps table: a list of L tensors [N][D][H>>l][W>>l][3] of dtype (float32 or
+    bfloat16), level 0 first. store: per-level booleans (levels not stored are None in the
+    result); out: preallocated tensors (or None entries) in place of fresh ones."""
+    codes = {torch.float32: HSGD_FP32, torch.bfloat16: HSGD_BF16}
+    if dtype not in codes:
+        raise TypeError("dtype must be float32 or bfloat16")
     _dev(images, "images")
     _f32(images, "images")
     if images.dim() != 4 or images.shape[-1] != 3:
@@ -409,14 +412,14 @@ def hsgd_plane_sweep(images: torch.Tensor, warps, D: int, L: int = 1, store=None
         t = None
         if out is not None and out[l] is not None:
             t = out[l]
-            if tuple(t.shape) != (N, D, H >> l, W >> l, 3) or t.dtype != torch.float32:
-                raise ValueError(f"out[{l}] must be float32 [{N}][{D}][{H >> l}][{W >> l}][3]")
+            if tuple(t.shape) != (N, D, H >> l, W >> l, 3) or t.dtype != dtype:
+                raise ValueError(f"out[{l}] must be {dtype} [{N}][{D}][{H >> l}][{W >> l}][3]")
             _dev(t, f"out[{l}]")
         elif store[l]:
-            t = torch.empty((N, D, H >> l, W >> l, 3), dtype=torch.float32, device=images.device)
+            t = torch.empty((N, D, H >> l, W >> l, 3), dtype=dtype, device=images.device)
         res.append(t)
     ptrs = (ctypes.c_void_p * L)(*[_ptr(t) for t in res])
-    _check(lib().hsgd_plane_sweep(ctypes.byref(v), D, L, ctypes.addressof(ptrs), _stream(stream)))
+    _check(lib().hsgd_plane_sweep(ctypes.byref(v), D, L, codes[dtype], ctypes.addressof(ptrs), _stream(stream)))
     return res
 
 

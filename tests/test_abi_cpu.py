@@ -101,18 +101,20 @@ def test_plane_sweep_validation():
     none3 = (ctypes.c_void_p * 3)(None, None, None)
     odd = (ctypes.c_void_p * 1)(FAKE + 4)
     ps = L.hsgd_plane_sweep
-    assert ps(None, 8, 3, three, None) == -1
-    assert ps(by(_views()), 8, 3, None, None) == -1
-    assert ps(by(_views(images=None)), 8, 3, three, None) == -1
-    assert ps(by(_views(warps=None)), 8, 3, three, None) == -1
-    assert ps(by(_views(N=0)), 8, 3, three, None) == -2
-    assert ps(by(_views()), 0, 3, three, None) == -2
-    assert ps(by(_views()), 65, 3, three, None) == -2
-    assert ps(by(_views()), 8, 0, three, None) == -2
-    assert ps(by(_views()), 8, 6, three, None) == -2
-    assert ps(by(_views(H=18)), 8, 3, three, None) == -2          # 18 is not a multiple of 4
-    assert ps(by(_views()), 8, 3, none3, None) == -1              # nothing to store
-    assert ps(by(_views()), 8, 1, odd, None) == -1                # misaligned output
+    assert ps(None, 8, 3, 0, three, None) == -1
+    assert ps(by(_views()), 8, 3, 0, None, None) == -1
+    assert ps(by(_views(images=None)), 8, 3, 0, three, None) == -1
+    assert ps(by(_views(warps=None)), 8, 3, 0, three, None) == -1
+    assert ps(by(_views(N=0)), 8, 3, 0, three, None) == -2
+    assert ps(by(_views()), 0, 3, 0, three, None) == -2
+    assert ps(by(_views()), 65, 3, 0, three, None) == -2
+    assert ps(by(_views()), 8, 0, 0, three, None) == -2
+    assert ps(by(_views()), 8, 6, 0, three, None) == -2
+    assert ps(by(_views(H=18)), 8, 3, 0, three, None) == -2          # 18 is not a multiple of 4
+    assert ps(by(_views()), 8, 3, 0, none3, None) == -1              # nothing to store
+    assert ps(by(_views()), 8, 3, 7, three, None) == -3             # unknown output type
+    assert ps(by(_views()), 8, 1, 1, odd, None) == -1                # misaligned output (BF16 too)
+    assert ps(by(_views()), 8, 1, 0, odd, None) == -1                # misaligned output
     assert "aligned" in L.hsgd_last_error().decode()
 
 

@@ -64,6 +64,27 @@ def test_plane_sweep_matches_oracle(case):
         assert err <= tol, (l, err)
 
 
+@pytest.mark.parametrize("case", [CASES[i] for i in (0, 1, 3, 4, 5)],
+                         ids=lambda c: f"seed{c[0]}_D{c[2]}_{c[3]}x{c[4]}_L{c[8]}")
+def test_plane_sweep_bf16_output(case):
+    """BF16 storage of every level: exactly the round-to-nearest-even of the FP32 output
+    (the levels are reduced in FP32 either way), and within half a BF16 ulp (plus the FP32
+    path's tolerance) of the oracle."""
+    seed, N, D, W, H, f, a, general, L, tol = case
+    rg, I = _psv_inputs(case)
+    table = hsgd.psv_warps(rg["K_ref"], rg["K"], rg["R"], rg["t"], rg["depths"], DEV)
+    Id = torch.from_numpy(I).float().to(DEV)
+    o32 = hsgd.hsgd_plane_sweep(Id, table, D, L)
+    o16 = hsgd.hsgd_plane_sweep(Id, table, D, L, dtype=torch.bfloat16)
+    torch.cuda.synchronize()
+    ref = _oracle(rg, I, L)
+    for l in range(L):
+        assert o16[l].dtype == torch.bfloat16
+        assert torch.equal(o16[l], o32[l].to(torch.bfloat16)), l
+        got = o16[l].float().cpu().numpy()
+        assert np.all(np.abs(got - ref[l]) <= 2.0 ** -8 * np.abs(ref[l]) + tol), l
+
+
 def test_plane_sweep_identity_pose_is_an_exact_copy():
     rg = rig(7, 2, 5, 70, 40, 50.0, 0.0)                     # zero translations
     I = f32(np.random.default_rng(8).uniform(size=(2, 40, 70, 3)))
