@@ -103,6 +103,20 @@ def refine_alg_bytes(D, shapes, iters, N, k, s):
     return total
 
 
+def host_info():
+    """The host the oracle is timed on: CPU model and logical core count."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "host_cores": os.cpu_count()}
+
+
 def cpu_baseline(name):
     """The FP64 oracle on the host, single-threaded: one full refine of the same workload,
     or, for the 1920x1080x64 frame, one finest-level iteration over a 1920x64 band of it
@@ -139,7 +153,7 @@ def cpu_baseline(name):
             dense = sum(n * sc.D * w * h for (w, h), n in zip(sc.shapes(), sc.iters))
             sample = (f"one full {len(sc.iters)}-level refine of the same {sc.W}x{sc.H}x{sc.D} scene "
                       f"(FP64 NumPy, {dt:.1f} s; targets rendered by the oracle, untimed)")
-    return {"value": dense / dt, "unit": "voxel-updates/s", "cores": 1, "kind": "oracle",
+    return {"value": dense / dt, "unit": "voxel-updates/s", "cores": 1, "kind": "oracle", **host_info(),
             "sample": sample}
 
 
@@ -331,7 +345,7 @@ def views_cpu_baseline():
         t0 = time.perf_counter()
         O.render(M, G)
         dt = time.perf_counter() - t0
-    return {"value": 3 / dt, "unit": "views/s", "cores": 1, "kind": "oracle",
+    return {"value": 3 / dt, "unit": "views/s", "cores": 1, "kind": "oracle", **host_info(),
             "sample": f"3 of the 18 novel views of a {sc.W}x{sc.H}x{sc.D} MPI (FP64 NumPy, {dt:.1f} s)"}
 
 
@@ -481,7 +495,7 @@ def psv_cpu_baseline(cfg, L):
                           sc.depths[:planes])
         O.psv_pyramid(P, L)
         dt = time.perf_counter() - t0
-    return {"value": nv * planes * sc.H * sc.W / dt, "unit": "PSV samples/s", "cores": 1, "kind": "oracle",
+    return {"value": nv * planes * sc.H * sc.W / dt, "unit": "PSV samples/s", "cores": 1, "kind": "oracle", **host_info(),
             "sample": f"{nv} view(s) x {planes} planes, {L} levels at {sc.W}x{sc.H} (FP64 NumPy, {dt:.1f} s)"}
 
 
