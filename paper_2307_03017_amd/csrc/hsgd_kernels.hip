@@ -443,17 +443,30 @@ __device__ __forceinline__ int slot_rank(uint64_t m, int z, int kcap) {
 // ------------------------------------------------------------------------------------
 // gradient, general warps: per-ray scans, atomic transposed-bilinear scatter
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ void scatter_tap(float4* __restrict__ slots, const uint64_t* __restrict__ mask,
-                                            uint64_t full, int kcap, int HW, int z, int p, float w,
-                                            const float4& g) {
-    if (w == 0.0f) return;
-    const int r = slot_rank(mask ? mask[p] : full, z, kcap);
+// Whole-wave lane shifts for the general-warp scatter: lane i <- lane i-1 / lane i+1; a lane
+// without a source gets `none`.
+__device__ __forceinline__ int lane_prev_i(int v, int none) {
+    return __builtin_amdgcn_update_dpp(none, v, 0x138, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int lane_next_i(int v, int none) {
+    return __builtin_amdgcn_update_dpp(none, v, 0x130, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float4 lane_prev_f4(float4 v) {
+    auto f = [](float a) { return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(a), 0x138, 0xF, 0xF, false)); };
+    return make_float4(f(v.x), f(v.y), f(v.z), f(v.w));
+}
+
+// One tap's contribution to the slots: cell c (-1: none) of plane z, value g.
+__device__ __forceinline__ void scatter_cell(float4* __restrict__ slots, const uint64_t* __restrict__ mask,
+                                             uint64_t full, int kcap, int HW, int z, int c, const float4& g) {
+    if (c < 0) return;
+    const int r = slot_rank(mask ? mask[c] : full, z, kcap);
     if (r < 0) return;
-    float* dst = reinterpret_cast<float*>(slots + (size_t)r * HW + p);
-    atomicAdd(dst + 0, w * g.x);
-    atomicAdd(dst + 1, w * g.y);
-    atomicAdd(dst + 2, w * g.z);
-    atomicAdd(dst + 3, w * g.w);
+    float* dst = reinterpret_cast<float*>(slots + (size_t)r * HW + c);
+    atomicAdd(dst + 0, g.x);
+    atomicAdd(dst + 1, g.y);
+    atomicAdd(dst + 2, g.z);
+    atomicAdd(dst + 3, g.w);
 }
 
 template <int DT, int MAXD>
@@ -473,25 +486,28 @@ __global__ __launch_bounds__(kBlock) void k_grad(const void* __restrict__ mpi, i
     const int y = blockIdx.y * kTileH + (threadIdx.x >> 6);
     const int HW = H * W;
     const uint64_t full = plane_bits(D);
+    // every lane runs both scans (a lane past the frame samples clamped taps and carries a
+    // zero residual), so that neighbouring lanes can merge their shared taps below
+    const bool ray = x < W && y < H;
     float sq = 0.0f;
-    if (x < W && y < H) {
-        float Ts[MAXD];
-        float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+    float Ts[MAXD];
+    float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
 #pragma unroll
-        for (int z = 0; z < MAXD; ++z) {
-            if (z < D) {
-                const Taps tp = make_taps(sw[z], x, y, H, W);
-                const float4 s = sample<DT>(mpi, z * HW, tp);
-                Ts[z] = T;
-                const float wgt = T * s.w;
-                c0 += wgt * s.x;
-                c1 += wgt * s.y;
-                c2 += wgt * s.z;
-                T *= 1.0f - s.w;
-            }
+    for (int z = 0; z < MAXD; ++z) {
+        if (z < D) {
+            const Taps tp = make_taps(sw[z], x, y, H, W);
+            const float4 s = sample<DT>(mpi, z * HW, tp);
+            Ts[z] = T;
+            const float wgt = T * s.w;
+            c0 += wgt * s.x;
+            c1 += wgt * s.y;
+            c2 += wgt * s.z;
+            T *= 1.0f - s.w;
         }
+    }
+    float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+    if (ray) {
         const size_t pix = ((size_t)view * H + y) * W + x;
-        float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
         if (images) {
             const float d0 = c0 - images[3 * pix + 0];
             const float d1 = c1 - images[3 * pix + 1];
@@ -506,29 +522,46 @@ __global__ __launch_bounds__(kBlock) void k_grad(const void* __restrict__ mpi, i
             g1 = dimg[3 * pix + 1];
             g2 = dimg[3 * pix + 2];
         }
-        float b0 = 0.0f, b1 = 0.0f, b2 = 0.0f;   // composite behind plane z
+    }
+    float b0 = 0.0f, b1 = 0.0f, b2 = 0.0f;   // composite behind plane z
 #pragma unroll
-        for (int zz = 0; zz < MAXD; ++zz) {
-            const int z = MAXD - 1 - zz;
-            if (z < D) {
-                const Taps tp = make_taps(sw[z], x, y, H, W);
-                const float4 s = sample<DT>(mpi, z * HW, tp);
-                const float Tz = Ts[z];
-                const float ca = s.w * Tz;
-                float4 gs;
-                gs.x = g0 * ca;
-                gs.y = g1 * ca;
-                gs.z = g2 * ca;
-                gs.w = Tz * (g0 * (s.x - b0) + g1 * (s.y - b1) + g2 * (s.z - b2));
-                const float oa = 1.0f - s.w;
-                b0 = s.w * s.x + oa * b0;
-                b1 = s.w * s.y + oa * b1;
-                b2 = s.w * s.z + oa * b2;
-                scatter_tap(slots, mask, full, kcap, HW, z, tp.i00, tp.w00, gs);
-                scatter_tap(slots, mask, full, kcap, HW, z, tp.i10, tp.w10, gs);
-                scatter_tap(slots, mask, full, kcap, HW, z, tp.i01, tp.w01, gs);
-                scatter_tap(slots, mask, full, kcap, HW, z, tp.i11, tp.w11, gs);
-            }
+    for (int zz = 0; zz < MAXD; ++zz) {
+        const int z = MAXD - 1 - zz;
+        if (z < D) {
+            const Taps tp = make_taps(sw[z], x, y, H, W);
+            const float4 s = sample<DT>(mpi, z * HW, tp);
+            const float Tz = Ts[z];
+            const float ca = s.w * Tz;
+            float4 gs;
+            gs.x = g0 * ca;
+            gs.y = g1 * ca;
+            gs.z = g2 * ca;
+            gs.w = Tz * (g0 * (s.x - b0) + g1 * (s.y - b1) + g2 * (s.z - b2));
+            const float oa = 1.0f - s.w;
+            b0 = s.w * s.x + oa * b0;
+            b1 = s.w * s.y + oa * b1;
+            b2 = s.w * s.z + oa * b2;
+            // the four taps (cell -1: no contribution): left column 00 / 01, right 10 / 11
+            int e00 = ray && tp.w00 != 0.0f ? tp.i00 : -1, e10 = ray && tp.w10 != 0.0f ? tp.i10 : -1;
+            int e01 = ray && tp.w01 != 0.0f ? tp.i01 : -1, e11 = ray && tp.w11 != 0.0f ? tp.i11 : -1;
+            float4 v00 = make_float4(tp.w00 * gs.x, tp.w00 * gs.y, tp.w00 * gs.z, tp.w00 * gs.w);
+            const float4 v10 = make_float4(tp.w10 * gs.x, tp.w10 * gs.y, tp.w10 * gs.z, tp.w10 * gs.w);
+            float4 v01 = make_float4(tp.w01 * gs.x, tp.w01 * gs.y, tp.w01 * gs.z, tp.w01 * gs.w);
+            const float4 v11 = make_float4(tp.w11 * gs.x, tp.w11 * gs.y, tp.w11 * gs.z, tp.w11 * gs.w);
+            // a right-column cell of lane i-1 that is lane i's left-column cell is added by
+            // lane i, once (the same equality on both sides: lane i merges exactly what lane
+            // i-1 drops), so neighbouring lanes of one atomic instruction rarely share a cell
+            const int p10 = lane_prev_i(e10, -1), p11 = lane_prev_i(e11, -1);
+            const float4 q10 = lane_prev_f4(v10), q11 = lane_prev_f4(v11);
+            const int n00 = lane_next_i(e00, -1), n01 = lane_next_i(e01, -1);
+            if (e00 >= 0 && p10 == e00) v00 = make_float4(v00.x + q10.x, v00.y + q10.y, v00.z + q10.z, v00.w + q10.w);
+            if (e01 >= 0 && p11 == e01) v01 = make_float4(v01.x + q11.x, v01.y + q11.y, v01.z + q11.z, v01.w + q11.w);
+            if (e10 >= 0 && n00 == e10) e10 = -1;
+            if (e11 >= 0 && n01 == e11) e11 = -1;
+            scatter_cell(slots, mask, full, kcap, HW, z, e00, v00);
+            scatter_cell(slots, mask, full, kcap, HW, z, e10, v10);
+            scatter_cell(slots, mask, full, kcap, HW, z, e01, v01);
+            scatter_cell(slots, mask, full, kcap, HW, z, e11, v11);
         }
     }
     if (partials) {
