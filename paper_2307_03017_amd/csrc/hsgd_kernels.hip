@@ -479,6 +479,10 @@ __global__ __launch_bounds__(kBlock) void k_grad(const void* __restrict__ mpi, i
                                                  float* __restrict__ partials) {
     __shared__ hsgd_warp sw[MAXD];
     __shared__ float sred[kBlock / 64];
+    // per plane parity: every lane's left-column tap cells (top, bottom) and its bottom-left
+    // contribution, for the row merge between neighbouring waves
+    __shared__ int s_cell[2][2][kBlock];
+    __shared__ float4 s_low[2][kBlock];
     const int view = blockIdx.z;
     load_warps(sw, warps, view, D);
     __syncthreads();
@@ -558,6 +562,18 @@ __global__ __launch_bounds__(kBlock) void k_grad(const void* __restrict__ mpi, i
             if (e01 >= 0 && p11 == e01) v01 = make_float4(v01.x + q11.x, v01.y + q11.y, v01.z + q11.z, v01.w + q11.w);
             if (e10 >= 0 && n00 == e10) e10 = -1;
             if (e11 >= 0 && n01 == e11) e11 = -1;
+            // the same between rows: a bottom-left cell of the wave above (same lane) that is
+            // this lane's top-left cell is added here, and dropped there
+            const int par = z & 1, t = threadIdx.x, wv = t >> 6;
+            s_cell[par][0][t] = e00;
+            s_cell[par][1][t] = e01;
+            s_low[par][t] = v01;
+            __syncthreads();   // (buffers alternate by plane: the next plane's writes go to the other)
+            if (wv > 0 && e00 >= 0 && s_cell[par][1][t - 64] == e00) {
+                const float4 a = s_low[par][t - 64];
+                v00 = make_float4(v00.x + a.x, v00.y + a.y, v00.z + a.z, v00.w + a.w);
+            }
+            if (wv + 1 < kTileH && e01 >= 0 && s_cell[par][0][t + 64] == e01) e01 = -1;
             scatter_cell(slots, mask, full, kcap, HW, z, e00, v00);
             scatter_cell(slots, mask, full, kcap, HW, z, e10, v10);
             scatter_cell(slots, mask, full, kcap, HW, z, e01, v01);
