@@ -39,12 +39,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=None, help="default 10 refines (100 requests for serving)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c5", "serving", "views18", "psv", "psv5"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c1", "c5", "c2g", "serving", "views18", "psv", "psv5"],
                     help="c2: 512x384x32 (the headline), c1: 64x48x8, c5: 1920x1080x64 8 views, "
                          "serving: the continuous-batching mix under Poisson arrivals, "
                          "views18: 18 novel views of a refined 512x384x32 MPI per step, "
                          "psv / psv5: the 3-level plane-sweep volume of the c2 rig / the 4-level "
-                         "one of the c5 rig per step")
+                         "one of the c5 rig per step, c2g: c2 with tilted cameras (general homographies)")
     ap.add_argument("--requests", type=int, default=1200, help="serving: measured requests")
     ap.add_argument("--rate", type=float, default=60.0, help="serving: mean arrivals per second")
     ap.add_argument("--dtype", default=None, choices=["fp32", "bf16"],
@@ -611,6 +611,7 @@ def main():
             "workload": (f"hsgd_refine {sc.W}x{sc.H}x{sc.D} planes, {sc.N} views, "
                          f"{len(sc.iters)} levels {'->'.join(f'{w}x{h}' for w, h in plan.shapes)}, "
                          f"iters {list(sc.iters)}, k={sc.k}, {args.dtype} storage"
+                         + (", tilted cameras (general plane homographies)" if args.workload == "c2g" else "")
                          + ("" if args.rule == "topk" else ", MVS-sampling selection")),
             "dense_voxel_updates_per_refine": dense,
             "active_voxel_updates_per_refine": active,

@@ -51,6 +51,11 @@ CONFIGS = {
     "s1008": dict(W=1008, H=756, D=32, N=5, f=787.5, a=0.1, levels=3, iters=(1, 1, 1), k=4, seed=106),
     # large XR frame: 1920x1080, 64 planes, 8 views, 4 levels (coarsest holds only the initial MPI)
     "c5": dict(W=1920, H=1080, D=64, N=8, f=1500.0, a=0.15, levels=4, iters=(0, 1, 1, 1), k=3, seed=5),
+    # the benchmark frame with tilted cameras: every view also rotated (Euler angles with a
+    # 0.01 rad standard deviation) and moved along z (within +-0.02), as hand-held
+    # forward-facing captures are, so its plane maps are general homographies
+    "c2g": dict(W=512, H=384, D=32, N=4, f=400.0, a=0.1, levels=3, iters=(1, 1, 1), k=4, seed=2,
+                tilt=0.01, tz=0.02),
 }
 
 ALPHA_EPS = 0.01
@@ -95,6 +100,7 @@ class Scene:
     seeds_xy: np.ndarray = field(repr=False, default=None)    # [D][24][2] in [0,1]^2
     seeds_rgb: np.ndarray = field(repr=False, default=None)   # [D][24][3]
     t: np.ndarray = field(repr=False, default=None)           # [N][3] camera translations
+    R: np.ndarray = field(repr=False, default=None)           # [N][3][3] camera rotations (identity unless tilted)
     init_noise_a: np.ndarray = field(repr=False, default=None)
     init_noise_c: np.ndarray = field(repr=False, default=None)
 
@@ -108,6 +114,8 @@ class Scene:
         return np.repeat(self.K_ref()[None], self.N, axis=0)
 
     def R_views(self) -> np.ndarray:
+        if self.R is not None:
+            return self.R.copy()
         return np.repeat(np.eye(3)[None], self.N, axis=0)
 
     def t_views(self) -> np.ndarray:
@@ -216,7 +224,8 @@ class Scene:
 
 def make_scene(name: str = "c1", seed: int | None = None, **overrides) -> Scene:
     """Draw a scene. Draw order: control grid, Voronoi seeds and colours per plane,
-    view translations, initial-MPI noise (alpha, then colour)."""
+    view translations, initial-MPI noise (alpha, then colour), then (tilted configs only)
+    view rotations and z translations."""
     cfg = dict(CONFIGS[name])
     cfg.update(overrides)
     if seed is not None:
@@ -236,7 +245,21 @@ def make_scene(name: str = "c1", seed: int | None = None, **overrides) -> Scene:
     w0, h0 = sc.shapes()[0]
     sc.init_noise_a = rng.standard_normal((sc.D, h0, w0))
     sc.init_noise_c = rng.standard_normal((sc.D, h0, w0, 3))
+    if cfg.get("tilt", 0.0) > 0.0:
+        # drawn last, so a tilted scene shares everything else with its untilted config
+        ang = rng.normal(0.0, cfg["tilt"], size=(sc.N, 3))
+        sc.R = np.stack([_euler(*a) for a in ang])
+        sc.t[:, 2] = rng.uniform(-cfg["tz"], cfg["tz"], size=sc.N)
     return sc
+
+
+def _euler(ax: float, ay: float, az: float) -> np.ndarray:
+    """Rotation Rz Ry Rx from Euler angles (radians)."""
+    cx, sx, cy, sy, cz, sz = np.cos(ax), np.sin(ax), np.cos(ay), np.sin(ay), np.cos(az), np.sin(az)
+    Rx = np.array([[1, 0, 0], [0, cx, -sx], [0, sx, cx]])
+    Ry = np.array([[cy, 0, sy], [0, 1, 0], [-sy, 0, cy]])
+    Rz = np.array([[cz, -sz, 0], [sz, cz, 0], [0, 0, 1]])
+    return Rz @ Ry @ Rx
 
 
 def random_mpi(rng: np.random.Generator, D: int, H: int, W: int, lo: float = 0.0,
