@@ -293,11 +293,13 @@ def test_refine_tiny_scene_teacher_forced():
             M = nxt
 
 
-@pytest.mark.parametrize("name,rule", [("c1", "topk"), ("c2", "topk"), ("c1", "mvs"), ("c2", "mvs")])
+@pytest.mark.parametrize("name,rule", [("c1", "topk"), ("c2", "topk"), ("c1", "mvs"), ("c2", "mvs"),
+                                       ("c2g", "topk")])
 def test_refine_end_to_end(name, rule):
     """hsgd_refine in one call vs the oracle refine: per-iteration losses and final PSNR,
-    with either selection rule. (No teacher forcing: FP32 drift may flip a near-tie
-    selection, so compare outcomes.)"""
+    with either selection rule, and on tilted cameras (general homographies, whose sample
+    positions the GPU evaluates in FP32: the looser bounds of the general-warp cases).
+    (No teacher forcing: FP32 drift may flip a near-tie selection, so compare outcomes.)"""
     sc, init, targets = scene_inputs(name)
     M_ref, log = O.refine(init, targets, sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(),
                           sc.depths, sc.iters, sc.k, 1.0, 1.0, rule=rule)
@@ -305,10 +307,19 @@ def test_refine_end_to_end(name, rule):
                                      sc.t_views(), sc.depths, sc.iters, sc.k, lr_rgb=1.0, lr_alpha=1.0,
                                      rule=rule)
     torch.cuda.synchronize()
+    general = name == "c2g"
     ref_losses = np.array([e["loss"] for e in log])
-    np.testing.assert_allclose(losses.cpu().numpy(), ref_losses, rtol=1e-4)
+    np.testing.assert_allclose(losses.cpu().numpy(), ref_losses, rtol=1e-3 if general else 1e-4)
     Mf = final.cpu().numpy().astype(np.float64)
-    assert np.abs(Mf - M_ref).max() <= 1e-3
+    diff = np.abs(Mf - M_ref)
+    print(f"{name}: final MPI max |diff| {diff.max():.2e}, mean {diff.mean():.2e}, "
+          f"{int(np.sum(diff > 1e-3))} values beyond 1e-3", flush=True)
+    if general:
+        # a near-tie selection may flip between the FP32 and FP64 positions: a handful of
+        # voxels then take one update more or less; everything else agrees
+        assert diff.mean() <= 1e-5 and np.mean(diff > 1e-3) <= 1e-5
+    else:
+        assert diff.max() <= 1e-3
     # PSNR of each side's final MPI, each rendered by its own side
     G = O.view_to_ref_maps(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths)
     p_ref = O.psnr(O.render(M_ref, G), targets)
