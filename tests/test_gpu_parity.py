@@ -187,6 +187,31 @@ def test_sparse_gradient_is_masked_dense_gradient(case):
     assert rel_err(g[S], g_ref[S]) <= rtol
 
 
+@pytest.mark.parametrize("general", [False, True], ids=["shift", "general"])
+def test_bf16_storage_gradient_matches_oracle(general):
+    """BF16 storage with FP32 arithmetic in the gradient kernels (translation and general
+    warps): the oracle's FP64 gradient of the BF16-rounded MPI, dense and restricted."""
+    seed, N, D, W, H = 26, 3, 12, 90, 50
+    rg, M, I = problem(seed, N, D, W, H, 60.0, 0.1, general, lo=0.05, hi=0.95)
+    Mq = bf16_vals(M)
+    L_ref, g_ref = O.loss_and_grad(Mq, oracle_maps(O, rg), I)
+    Md = to_dev(Mq, torch.bfloat16)
+    table = device_warps(hsgd, rg)
+    assert table.shift_only == (not general)
+    g, loss = hsgd.hsgd_grad_step(Md, table, N, images=to_dev(I), want_grad=True, want_loss=True)
+    rtol = 1e-3 if general else GRAD_RTOL
+    assert rel_err(g.cpu().numpy(), g_ref) <= rtol
+    assert abs(loss.item() - L_ref) <= (1e-4 if general else 1e-5) * L_ref
+    k = 3
+    mask = hsgd.hsgd_select_active(Md, k, with_ids=False)
+    gs, _ = hsgd.hsgd_grad_step(Md, table, N, images=to_dev(I), mask=mask, kcap=k, want_grad=True)
+    S = mask_bits(mask.cpu().numpy(), D)
+    assert np.array_equal(S, O.select_active(Mq[..., 3], k))
+    gs = gs.cpu().numpy()
+    assert np.all(gs[~S] == 0.0)
+    assert rel_err(gs[S], g_ref[S]) <= rtol
+
+
 def test_vjp_matches_oracle():
     rg, M, _ = problem(30, 3, 11, 77, 41, 60.0, 0.08, lo=0.05, hi=0.95)
     rng = np.random.default_rng(31)
