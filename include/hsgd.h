@@ -10,9 +10,12 @@
  *              composite with the over operator (Eq. render, Eq. over);
  *   grad    -- photometric loss against the views and its exact gradient, pushed back
  *              through compositing and the bilinear warp, kept only on the selected voxels;
- *   update  -- analytic descent (Eq. 4 with no prior) restored onto the selected voxels
- *              (the M_{n+1} = M_n + R(., S) update), clamped to [0, 1].
+ *   update  -- analytic descent (Eq. 4; the sparsity prior of Sec. 3.4 optional, weight
+ *              lambda_s) restored onto the selected voxels (the M_{n+1} = M_n + R(., S)
+ *              update), clamped to [0, 1].
  * Levels run coarse to fine (Sec. 3.2: H/2^l x W/2^l), the MPI upsampled 2x in between.
+ * Also exported: the hierarchical plane-sweep volume (Sec. 3.2) and a continuous-batching
+ * serving core. tests/hsgd_c_smoke.c shows the calls used from plain C.
  *
  * Conventions for every call:
  *  - Layouts. MPI: [D][H][W][4] straight (non-premultiplied) RGBA in [0, 1], plane z = 0 the

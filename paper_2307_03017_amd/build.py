@@ -19,6 +19,9 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhsgd.so")
+# a plain-C program driving the library through include/hsgd.h alone (run by the GPU tests)
+C_SMOKE_SRC = os.path.join(ROOT, "tests", "hsgd_c_smoke.c")
+C_SMOKE = os.path.join(PKG, "hsgd_c_smoke")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -72,6 +75,10 @@ def build(verbose: bool = False) -> str:
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp,
           *[o for _, o in jobs], "-L/opt/rocm/lib", "-lamdhip64"])
     os.replace(tmp, LIB)
+    if os.path.exists(C_SMOKE_SRC):
+        _run(["gcc", "-std=c11", "-O2", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__", "-I", INCLUDE,
+              "-I", "/opt/rocm/include", C_SMOKE_SRC, "-L", PKG, "-lhsgd", "-L/opt/rocm/lib", "-lamdhip64",
+              "-lm", "-Wl,-rpath,$ORIGIN", "-Wl,-rpath,/opt/rocm/lib", "-o", C_SMOKE])
     return LIB
 
 
