@@ -117,6 +117,18 @@ def host_info():
     return {"cpu_model": model, "host_cores": os.cpu_count()}
 
 
+def timed_runs(fn, min_s=10.0, max_runs=8):
+    """Runs fn until at least min_s seconds have passed (at most max_runs times); returns the
+    mean seconds per run and the number of runs."""
+    runs, total = 0, 0.0
+    while runs < max_runs and (runs == 0 or total < min_s):
+        t0 = time.perf_counter()
+        fn()
+        total += time.perf_counter() - t0
+        runs += 1
+    return total / runs, runs
+
+
 def cpu_baseline(name):
     """The FP64 oracle on the host, single-threaded: one full refine of the same workload,
     or, for the 1920x1080x64 frame, one finest-level iteration over a 1920x64 band of it
@@ -134,25 +146,24 @@ def cpu_baseline(name):
             band = 32
             M = scenes.random_mpi(rng, sc.D, band, sc.W, 0.05, 0.95)
             I = scenes.random_images(rng, sc.N, band, sc.W)
-            t0 = time.perf_counter()
-            S = O.select_active(M[..., 3].astype(np.float32), sc.k)
-            _, g = O.loss_and_grad(M, G, I)
-            O.apply_update(M, g, S, 1.0, 1.0, bf16=True)
-            dt = time.perf_counter() - t0
+            def one():
+                S = O.select_active(M[..., 3].astype(np.float32), sc.k)
+                _, g = O.loss_and_grad(M, G, I)
+                O.apply_update(M, g, S, 1.0, 1.0, bf16=True)
+
+            dt, runs = timed_runs(one)
             dense = sc.D * band * sc.W
             sample = (f"one finest-level iteration (select, render + loss, adjoint, BF16 update) "
                       f"over a {sc.W}x{band} band of the {sc.W}x{sc.H}x{sc.D} frame, {sc.N} views "
-                      f"(FP64 NumPy, {dt:.1f} s), per dense voxel-update")
+                      f"(FP64 NumPy, {runs} runs of {dt:.1f} s), per dense voxel-update")
         else:
             targets = O.render(sc.gt_mpi(), G)           # untimed input preparation
             init = sc.initial_mpi()
-            t0 = time.perf_counter()
-            O.refine(init, targets, sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths,
-                     sc.iters, sc.k, 1.0, 1.0)
-            dt = time.perf_counter() - t0
+            dt, runs = timed_runs(lambda: O.refine(init, targets, sc.K_ref(), sc.K_views(), sc.R_views(),
+                                                   sc.t_views(), sc.depths, sc.iters, sc.k, 1.0, 1.0))
             dense = sum(n * sc.D * w * h for (w, h), n in zip(sc.shapes(), sc.iters))
-            sample = (f"one full {len(sc.iters)}-level refine of the same {sc.W}x{sc.H}x{sc.D} scene "
-                      f"(FP64 NumPy, {dt:.1f} s; targets rendered by the oracle, untimed)")
+            sample = (f"full {len(sc.iters)}-level refines of the same {sc.W}x{sc.H}x{sc.D} scene "
+                      f"(FP64 NumPy, {runs} runs of {dt:.1f} s; targets rendered by the oracle, untimed)")
     return {"value": dense / dt, "unit": "voxel-updates/s", "cores": 1, "kind": "oracle", **host_info(),
             "sample": sample}
 
@@ -342,11 +353,9 @@ def views_cpu_baseline():
     G = O.view_to_ref_maps(sc.K_ref(), K[:3], R[:3], t[:3], sc.depths)
     M = sc.noisy_mpi(sc.W, sc.H, seed=77).astype(np.float64)
     with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        O.render(M, G)
-        dt = time.perf_counter() - t0
+        dt, runs = timed_runs(lambda: O.render(M, G))
     return {"value": 3 / dt, "unit": "views/s", "cores": 1, "kind": "oracle", **host_info(),
-            "sample": f"3 of the 18 novel views of a {sc.W}x{sc.H}x{sc.D} MPI (FP64 NumPy, {dt:.1f} s)"}
+            "sample": f"3 of the 18 novel views of a {sc.W}x{sc.H}x{sc.D} MPI (FP64 NumPy, {runs} runs of {dt:.1f} s)"}
 
 
 def l2_hit_rate(kernel, workload):
@@ -489,14 +498,16 @@ def psv_cpu_baseline(cfg, L):
     sc = scenes.make_scene(cfg)
     nv, planes = (sc.N, sc.D) if cfg == "c2" else (1, 16)
     I = np.random.default_rng(3).uniform(size=(nv, sc.H, sc.W, 3))
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
+    def one():
         P = O.plane_sweep(I, sc.K_ref(), sc.K_views()[:nv], sc.R_views()[:nv], sc.t_views()[:nv],
                           sc.depths[:planes])
         O.psv_pyramid(P, L)
-        dt = time.perf_counter() - t0
-    return {"value": nv * planes * sc.H * sc.W / dt, "unit": "PSV samples/s", "cores": 1, "kind": "oracle", **host_info(),
-            "sample": f"{nv} view(s) x {planes} planes, {L} levels at {sc.W}x{sc.H} (FP64 NumPy, {dt:.1f} s)"}
+
+    with threadpool_limits(limits=1):
+        dt, runs = timed_runs(one)
+    return {"value": nv * planes * sc.H * sc.W / dt, "unit": "PSV samples/s", "cores": 1, "kind": "oracle",
+            **host_info(), "sample": (f"{nv} view(s) x {planes} planes, {L} levels at {sc.W}x{sc.H} "
+                                      f"(FP64 NumPy, {runs} runs of {dt:.1f} s)")}
 
 
 def main():
