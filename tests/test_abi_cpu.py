@@ -94,6 +94,24 @@ def test_psv_translation_split_is_exact():
             assert abs(w.iy + float(w.fy) - s[1]) < 1e-6
 
 
+def test_psv_warps_reject_bad_input():
+    K = np.eye(3)
+    for fn in (hsgd.hsgd_build_psv_warps, hsgd.hsgd_build_warps):
+        with pytest.raises(hsgd.HsgdError) as e:
+            fn(K, K[None], np.eye(3)[None], np.zeros((1, 3)), np.array([1.0, 0.0]))      # depth 0
+        assert e.value.status == -1
+        with pytest.raises(hsgd.HsgdError) as e:
+            fn(np.zeros((3, 3)), K[None], np.eye(3)[None], np.zeros((1, 3)), np.array([1.0]))
+        assert e.value.status == -1
+        with pytest.raises(hsgd.HsgdError) as e:
+            fn(K, np.repeat(K[None], 65, 0), np.repeat(np.eye(3)[None], 65, 0), np.zeros((65, 3)),
+               np.array([1.0]))                                                           # N > 64
+        assert e.value.status == -2
+    L = hsgd.lib()
+    assert L.hsgd_build_psv_warps(None, None, None, None, None, 1, 1, None) == -1
+    assert "hsgd_build_psv_warps" in L.hsgd_last_error().decode()
+
+
 def test_plane_sweep_validation():
     L = hsgd.lib()
     by = ctypes.byref
