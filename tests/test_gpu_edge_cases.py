@@ -1,6 +1,7 @@
 """Degenerate cases of the method on the GPU, each against the FP64 oracle: one plane and one
 view on the smallest frame, a view whose planes all land outside the frame, a mask that
-keeps every plane, a single-level refine, and the smallest plane-sweep volumes."""
+keeps every plane, the maximum view and plane counts, a single-level refine, a refine with
+no iterations, and the smallest plane-sweep volumes."""
 
 import numpy as np
 import pytest
@@ -121,3 +122,46 @@ def test_smallest_plane_sweeps():
     P = hsgd.hsgd_plane_sweep(to_dev(I), hsgd.psv_warps(rg["K_ref"], rg["K"], rg["R"], rg["t"], rg["depths"], DEV),
                               D, 2)
     assert all(torch.count_nonzero(p).item() == 0 for p in P)
+
+
+def test_maximum_views_and_planes():
+    # 64 views and 64 planes (every bit of the plane mask word), k = 64 and a sparse k
+    W, H, D, N, f = 16, 8, 64, 64, 10.0
+    rng = np.random.default_rng(75)
+    t = rng.uniform(-0.05, 0.05, size=(N, 2))
+    rg = shift_rig(W, H, D, f, t)
+    M = f32(rng.uniform(0.05, 0.95, size=(D, H, W, 4)))
+    I = f32(rng.uniform(size=(N, H, W, 3)))
+    G = oracle_maps(O, rg)
+    table = device_warps(hsgd, rg)
+    Md = to_dev(M)
+    out, loss = hsgd.hsgd_render(Md, table, N, images=to_dev(I), want_loss=True)
+    assert np.abs(out.cpu().numpy() - O.render(M, G)).max() <= 1e-5
+    L_ref, g_ref = O.loss_and_grad(M, G, I)
+    assert abs(loss.item() - L_ref) <= 1e-5 * L_ref
+    for k in (64, 5):
+        mask = hsgd.hsgd_select_active(Md, k, with_ids=False)
+        S = mask_bits(mask.cpu().numpy(), D)
+        assert np.array_equal(S, O.select_active(M[..., 3], k))
+        g, _ = hsgd.hsgd_grad_step(Md, table, N, images=to_dev(I), mask=mask, kcap=k, want_grad=True)
+        g = g.cpu().numpy()
+        assert np.all(g[~S] == 0.0)
+        assert rel_err(g[S], g_ref[S]) <= 1e-4
+    # the update with every view's slice summed (the update kernel's largest view table)
+    M2 = Md.clone()
+    mask = hsgd.hsgd_select_active(Md, 5, with_ids=False)
+    hsgd.hsgd_grad_step(M2, table, N, images=to_dev(I), mask=mask, kcap=5, lr_rgb=0.5, lr_alpha=0.5)
+    S = mask_bits(mask.cpu().numpy(), D)
+    exp = O.apply_update(M, g_ref, S, 0.5, 0.5)
+    assert np.abs(M2.cpu().numpy() - exp).max() <= 1e-5
+
+
+def test_refine_with_no_iterations_only_upsamples():
+    sc = scenes.make_scene("c1")
+    M0 = f32(sc.initial_mpi())
+    G = O.view_to_ref_maps(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths)
+    targets = O.render(sc.gt_mpi(), G)
+    out, losses = hsgd.hsgd_refine(to_dev(M0), to_dev(targets), sc.K_ref(), sc.K_views(), sc.R_views(),
+                                   sc.t_views(), sc.depths, (0, 0), sc.k)
+    assert losses.numel() == 0
+    assert np.abs(out.cpu().numpy() - O.upsample2x(M0)).max() <= 1e-6
