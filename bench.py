@@ -633,7 +633,8 @@ def main():
         "active_voxel_updates_per_s": active * K / wall,
         "loss_log": final_loss,
         "roofline": {
-            "kernel": "k_grad",
+            # the translation-warp specialisation on pure-translation rigs, else the general kernel
+            "kernel": "k_grad_shift" if all(w.shift_only for w in plan.warps) else "k_grad",
             "bound": "alu" if alu_bound else "hbm",
             "achieved": achieved_tf if alu_bound else achieved_gbs,
             "peak": FP32_VECTOR_PEAK_TFLOPS if alu_bound else HBM_PEAK_GBS,
