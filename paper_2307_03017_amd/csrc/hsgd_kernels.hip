@@ -634,6 +634,12 @@ __device__ __forceinline__ void grad_shift_tile(
     __shared__ float4 s_w[kSY][MAXD];                       // per wave row and plane: tap weights
     __shared__ float2 s_f[MAXD];                            // per plane: the shift's fraction
     __shared__ uint32_t s_code[(MAXD + 3) / 4][kSX * kSY];  // rank bytes of 4 planes per thread
+    // Transmittance in front of the first kTL planes: these live longest (from the start of
+    // the front-to-back scan to the end of the back-to-front one), so at 6 waves per SIMD
+    // they go to LDS instead of registers, which would otherwise spill to scratch memory
+    // (whose reloads wait for every load in flight, the look-ahead included).
+    constexpr int kTL = MAXD <= 32 ? 4 : 0;
+    __shared__ float s_T[kTL > 0 ? kTL : 1][kSX * kSY];
     const int view = tile % N;
     const int t2 = tile / N;
     const int tx = t2 % ntx, ty = t2 / ntx;
@@ -752,7 +758,10 @@ __device__ __forceinline__ void grad_shift_tile(
                 qm[z % kAhead] = fetch_mask(q[z % kAhead]);
             }
             const float4 s = sample(z, cur);
-            Ts[z] = T;
+            if (z < kTL)
+                s_T[z < kTL ? z : 0][tid] = T;
+            else
+                Ts[z] = T;
             const float wgt = T * s.w;
             c0 += wgt * s.x;
             c1 += wgt * s.y;
@@ -835,7 +844,7 @@ __device__ __forceinline__ void grad_shift_tile(
             const float4 s = sample(z, cur);
             float4* buf = s_h[z & 1];
             if ((need_bits >> z) & 1) {
-                const float Tz = Ts[z];
+                const float Tz = z < kTL ? s_T[z < kTL ? z : 0][tid] : Ts[z];
                 const float ca = s.w * Tz;
                 float4 a;
                 a.x = g0 * ca;
