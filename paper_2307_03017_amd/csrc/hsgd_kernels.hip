@@ -894,8 +894,8 @@ __device__ __forceinline__ void grad_shift_tile(
     }
 }
 
-// Up to 32 planes the kernel is held to 6 waves per SIMD (3 workgroups per CU): the
-// occupancy gained outweighs the one or two registers that spill.
+// Up to 32 planes the kernel is held to 6 waves per SIMD (3 workgroups per CU), within
+// 80 registers and without spills (the first planes' transmittance is kept in LDS).
 template <int DT, int MAXD, bool MASKED>
 __global__ __launch_bounds__(kSX * kSY) __attribute__((amdgpu_waves_per_eu(MAXD <= 32 ? 6 : 1))) void k_grad_shift(
     const void* __restrict__ mpi, int D, int H, int W, int N, const hsgd_warp* __restrict__ warps,

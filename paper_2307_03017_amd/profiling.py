@@ -31,11 +31,18 @@ KERNEL_SOURCES = {
 DEFAULT_SOURCES = ("hsgd_kernels.hip", "hsgd_device.h", "hsgd_internal.h")
 
 
+_COMMENT = re.compile(r"//[^\n]*|/\*.*?\*/", re.S)
+
+
 def kernel_source_hash(kernel: str = "k_grad_shift") -> str:
+    """Hash of the code a kernel is compiled from: its sources with comments removed and
+    whitespace collapsed, so that editing a comment keeps the recorded figures valid."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES.get(kernel, DEFAULT_SOURCES):
-        with open(os.path.join(_PKG, "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(_PKG, "csrc", f), encoding="utf-8") as fh:
+            code = " ".join(_COMMENT.sub(" ", fh.read()).split())
+        h.update(code.encode())
+        h.update(b"\0")
     return h.hexdigest()[:16]
 
 
