@@ -784,8 +784,8 @@ __device__ __forceinline__ void grad_shift_tile(
         }
         // The look-ahead loads are consumed on the path out of the loop as well, so that
         // each is issued before its plane's branch rather than sunk to its use two planes
-        // later. Up to 32 planes that hides the load latency; with 64 planes the registers
-        // it holds cost a wave per SIMD, which loses more than it hides.
+        // later. Up to 32 planes that hides the load latency; with 64 planes (4 waves per
+        // SIMD with or without it) it measured slower, so there the loads sink to their use.
         if constexpr (MAXD <= 32)
             asm volatile("" ::"v"(q[0].t00.x), "v"(q[0].t01.x), "v"((uint32_t)qm[0]), "v"(q[1].t00.x),
                          "v"(q[1].t01.x), "v"((uint32_t)qm[1]));
