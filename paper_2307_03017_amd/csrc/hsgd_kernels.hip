@@ -620,6 +620,16 @@ __device__ __forceinline__ float rlf(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
+// Bilinear sample of a translation warp, one channel: this lane holds its column of the
+// two tap rows (a0 above, a1 below), the next lane the column to the right. Vertical lerp
+// of the own column, then the horizontal lerp with the next lane's (4 instructions, the
+// lane shift folded into a multiply). wt = (upper row weight, lower row weight, 1 - fx,
+// fx), a row outside the plane weighted 0.
+__device__ __forceinline__ float lerp_taps(float a0, float a1, const float4& wt) {
+    const float v = __builtin_fmaf(a1, wt.y, a0 * wt.x);
+    return __builtin_fmaf(v, wt.z, lane_from_next(v) * wt.w);
+}
+
 // One 64 x 8 tile of one view (tile = view + N * (tx + ntx * ty)); every thread of the
 // workgroup calls it.
 template <int DT, int MAXD, bool MASKED>
@@ -653,9 +663,9 @@ __device__ __forceinline__ void grad_shift_tile(
     const uint64_t full = plane_bits(D);
 
     // Plane tables. Lane z < D holds plane z's integer shift (read per plane with
-    // v_readlane: it feeds scalar address arithmetic). The four bilinear weights of each
-    // plane for this wave's row (taps in rows outside the plane zeroed) and the shift's
-    // fraction go to LDS, read per plane as broadcasts. Planes z >= D get zeros.
+    // v_readlane: it feeds scalar address arithmetic). The bilinear weights of each plane
+    // for this wave's row (lerp_taps' four; a tap row outside the plane weighted 0) and the
+    // shift's fraction go to LDS, read per plane as broadcasts. Planes z >= D get zeros.
     int lx = 0, ly = 0;
     if (lane < MAXD) {
         float4 wt = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -668,7 +678,7 @@ __device__ __forceinline__ void grad_shift_tile(
             const int Y0 = y + ly;
             const float gy = (unsigned)Y0 < (unsigned)H ? 1.0f - fr.y : 0.0f;
             const float hy = (unsigned)(Y0 + 1) < (unsigned)H ? fr.y : 0.0f;
-            wt = make_float4((1.0f - fr.x) * gy, fr.x * gy, (1.0f - fr.x) * hy, fr.x * hy);
+            wt = make_float4(gy, hy, 1.0f - fr.x, fr.x);
         }
         s_w[wv][lane] = wt;
         if (wv == 0) s_f[lane] = fr;
@@ -717,14 +727,11 @@ __device__ __forceinline__ void grad_shift_tile(
     };
     auto sample = [&](int z, const Taps2& f) {
         const float4 wt = s_w[wv][z];
-        const float w00 = wt.x, w10 = wt.y, w01 = wt.z, w11 = wt.w;
-        // left column of both tap rows from this lane; the right column's weighted sum is
-        // formed by the next lane on its own taps and added through DPP
         float4 s;
-        s.x = __builtin_fmaf(f.t01.x, w01, f.t00.x * w00) + lane_from_next(__builtin_fmaf(f.t01.x, w11, f.t00.x * w10));
-        s.y = __builtin_fmaf(f.t01.y, w01, f.t00.y * w00) + lane_from_next(__builtin_fmaf(f.t01.y, w11, f.t00.y * w10));
-        s.z = __builtin_fmaf(f.t01.z, w01, f.t00.z * w00) + lane_from_next(__builtin_fmaf(f.t01.z, w11, f.t00.z * w10));
-        s.w = __builtin_fmaf(f.t01.w, w01, f.t00.w * w00) + lane_from_next(__builtin_fmaf(f.t01.w, w11, f.t00.w * w10));
+        s.x = lerp_taps(f.t00.x, f.t01.x, wt);
+        s.y = lerp_taps(f.t00.y, f.t01.y, wt);
+        s.z = lerp_taps(f.t00.z, f.t01.z, wt);
+        s.w = lerp_taps(f.t00.w, f.t01.w, wt);
         return s;
     };
     constexpr int kAhead = 2;
@@ -939,7 +946,7 @@ __global__ __launch_bounds__(kSX * kSY) void k_render_shift(const void* __restri
             const int Y0 = y + ly;
             const float gy = (unsigned)Y0 < (unsigned)H ? 1.0f - w.fy : 0.0f;
             const float hy = (unsigned)(Y0 + 1) < (unsigned)H ? w.fy : 0.0f;
-            wt = make_float4((1.0f - w.fx) * gy, w.fx * gy, (1.0f - w.fx) * hy, w.fx * hy);
+            wt = make_float4(gy, hy, 1.0f - w.fx, w.fx);
         }
         s_w[wv][lane] = wt;
     }
@@ -976,10 +983,10 @@ __global__ __launch_bounds__(kSX * kSY) void k_render_shift(const void* __restri
             if (z + kAhead < MAXD) q[z % kAhead] = fetch(z + kAhead);
             const float4 wt = s_w[wv][z];
             float4 s;
-            s.x = __builtin_fmaf(f.t01.x, wt.z, f.t00.x * wt.x) + lane_from_next(__builtin_fmaf(f.t01.x, wt.w, f.t00.x * wt.y));
-            s.y = __builtin_fmaf(f.t01.y, wt.z, f.t00.y * wt.x) + lane_from_next(__builtin_fmaf(f.t01.y, wt.w, f.t00.y * wt.y));
-            s.z = __builtin_fmaf(f.t01.z, wt.z, f.t00.z * wt.x) + lane_from_next(__builtin_fmaf(f.t01.z, wt.w, f.t00.z * wt.y));
-            s.w = __builtin_fmaf(f.t01.w, wt.z, f.t00.w * wt.x) + lane_from_next(__builtin_fmaf(f.t01.w, wt.w, f.t00.w * wt.y));
+            s.x = lerp_taps(f.t00.x, f.t01.x, wt);
+            s.y = lerp_taps(f.t00.y, f.t01.y, wt);
+            s.z = lerp_taps(f.t00.z, f.t01.z, wt);
+            s.w = lerp_taps(f.t00.w, f.t01.w, wt);
             const float wgt = T * s.w;
             c0 += wgt * s.x;
             c1 += wgt * s.y;
