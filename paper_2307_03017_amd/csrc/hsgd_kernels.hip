@@ -1197,31 +1197,49 @@ __global__ __launch_bounds__(256) void k_upsample(const void* __restrict__ src, 
     upsample_voxel<DT>(src, h, w, dst, blockIdx.y, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// Upsampling fused with the first selection at the new level: one thread per output pixel
-// writes its D voxels and scores the alpha it stored (the storage-rounded value), so the
-// mask equals what k_select computes from the stored level.
+// Upsampling fused with the first selection at the new level. A block covers 64 output
+// pixels (lane = pixel) and its four waves split the planes: each upsamples and stores a
+// quarter of them and puts the alpha it stored (the storage-rounded value) in LDS; the
+// first wave then scores every plane of its pixel front to back and writes the mask, which
+// equals what k_select computes from the stored level. Splitting the planes shortens each
+// thread's chain of dependent tap loads and gives the small levels four times the waves.
+constexpr int kUpWaves = 4;
 template <int DT, int MAXD>
-__global__ __launch_bounds__(256) void k_upsample_select(const void* __restrict__ src, int D, int h, int w,
-                                                         void* __restrict__ dst, int k, float tau, int rule,
-                                                         uint64_t* __restrict__ mask) {
-    const int W2 = 2 * w, H2 = 2 * h;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= W2 * H2) return;
-    float A[MAXD];
-    float T = 1.0f;
-    // planes in groups of 4: the group's 16 tap loads are in flight together (plane index
-    // clamped, so they need no guard)
-    constexpr int kG = 4;
+__global__ __launch_bounds__(64 * kUpWaves) void k_upsample_select(const void* __restrict__ src, int D, int h,
+                                                                   int w, void* __restrict__ dst, int k,
+                                                                   float tau, int rule,
+                                                                   uint64_t* __restrict__ mask) {
+    constexpr int kPW = (MAXD + kUpWaves - 1) / kUpWaves;   // planes per wave
+    constexpr int kG = kPW < 4 ? kPW : 4;                    // tap loads of kG planes in flight together
+    static_assert(kPW % kG == 0, "whole load groups");
+    __shared__ float s_a[kUpWaves * kPW][64];
+    const int n = 4 * w * h;
+    const int lane = threadIdx.x & 63;
+    const int q = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int i = blockIdx.x * 64 + lane;
+    if (i < n) {
 #pragma unroll
-    for (int z0 = 0; z0 < MAXD; z0 += kG) {
-        UpTaps<DT> t[kG];
+        for (int j0 = 0; j0 < kPW; j0 += kG) {
+            // plane index clamped, so the loads need no guard
+            UpTaps<DT> t[kG];
 #pragma unroll
-        for (int j = 0; j < kG; ++j) t[j] = upsample_taps<DT>(src, h, w, min(z0 + j, D - 1), i);
+            for (int j = 0; j < kG; ++j) t[j] = upsample_taps<DT>(src, h, w, min(q * kPW + j0 + j, D - 1), i);
 #pragma unroll
-        for (int j = 0; j < kG; ++j)
-            if (z0 + j < D) A[z0 + j] = score_step(upsample_store<DT>(t[j], dst, W2 * H2, z0 + j, i).w, T);
+            for (int j = 0; j < kG; ++j) {
+                const int z = q * kPW + j0 + j;
+                if (z < D) s_a[z][lane] = upsample_store<DT>(t[j], dst, n, z, i).w;
+            }
+        }
     }
-    mask[i] = topk_bits<MAXD>(A, D, k, tau, rule);
+    __syncthreads();
+    if (q == 0 && i < n) {
+        float A[MAXD];
+        float T = 1.0f;
+#pragma unroll
+        for (int z = 0; z < MAXD; ++z)
+            if (z < D) A[z] = score_step(s_a[z][lane], T);
+        mask[i] = topk_bits<MAXD>(A, D, k, tau, rule);
+    }
 }
 
 // Output pixel i of view n of the 2x2 box mean of [N][H][W][3] images.
@@ -1490,9 +1508,9 @@ int launch_upsample(const hsgd_mpi& c, const hsgd_mpi& f, hipStream_t s) {
 
 int launch_upsample_select(const hsgd_mpi& c, const hsgd_mpi& f, int k, float tau, int rule, uint64_t* mask,
                            hipStream_t s) {
-    const dim3 grid((unsigned)ceil_div((int64_t)f.H * f.W, 256));
+    const dim3 grid((unsigned)ceil_div((int64_t)f.H * f.W, 64));
     ProfScope ps(HSGD_K_UPSAMPLE, s);
-    HSGD_DISPATCH_T(c.dtype, HSGD_DISPATCH_D(c.D, hipLaunchKernelGGL((k_upsample_select<DT, MD>), grid, dim3(256), 0, s,
+    HSGD_DISPATCH_T(c.dtype, HSGD_DISPATCH_D(c.D, hipLaunchKernelGGL((k_upsample_select<DT, MD>), grid, dim3(64 * kUpWaves), 0, s,
                                                                     c.rgba, c.D, c.H, c.W, f.rgba, k, tau, rule,
                                                                     mask)));
     return (int)hipGetLastError();
