@@ -1029,9 +1029,11 @@ __global__ __launch_bounds__(256) void k_fill_zero(float4* __restrict__ p, int64
 // warps, view v wrote voxel (z, p) only if p lies in v's owner coverage for plane z;
 // outside it no ray of v reaches the voxel and the slot is not read. Workgroup 0 also
 // reduces the loss partials of the gradient kernel (fixed order, FP64).
-// Workgroup blk of the update over one MPI level (256 pixels); s_off is LDS for the
-// [nslices][D] shifts. Every thread of the workgroup calls it.
-template <int DT, bool SHIFT>
+// Workgroup blk of the update over one MPI level (256 / RS pixels: with RS > 1 the RS
+// groups of 256 / RS threads take the selected planes of rank r = group (mod RS) of the
+// same pixels, so the ranks of a pixel are updated in parallel); s_off is LDS for the
+// [nslices][D] shifts. Every thread of the 256-thread workgroup calls it.
+template <int DT, bool SHIFT, int RS = 1>
 __device__ __forceinline__ void update_block(void* __restrict__ mpi, int D, int H, int W,
                                              const uint64_t* __restrict__ mask, int kcap,
                                              const float4* __restrict__ slots, int nslices,
@@ -1057,8 +1059,11 @@ __device__ __forceinline__ void update_block(void* __restrict__ mpi, int D, int 
         }
         if (threadIdx.x == 0) *out_loss = (float)(sh[0] * loss_scale);
     }
+    static_assert(256 % RS == 0, "whole pixel groups");
+    constexpr int kPix = 256 / RS;
     const int HW = H * W;
-    const int p = blk * blockDim.x + threadIdx.x;
+    const int p = blk * kPix + (int)(threadIdx.x % kPix);
+    const int q = (int)(threadIdx.x / kPix);
     if (p >= HW) return;
     const int Y = p / W, X = p - Y * W;
     const uint64_t m = (mask ? mask[p] : ~0ull) & plane_bits(D);
@@ -1101,9 +1106,11 @@ __device__ __forceinline__ void update_block(void* __restrict__ mpi, int D, int 
     while (b && r < kcap) {
         const int z = __ffsll((unsigned long long)b) - 1;
         b &= b - 1;
+        const int rank = r++;
+        if (RS > 1 && rank % RS != q) continue;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (do_update || prior != 0.0f) v = Vox<DT>::load(mpi, z * HW + p);   // in flight with the slices
-        float4 g = grad_of(z, r++);
+        float4 g = grad_of(z, rank);
         if (prior != 0.0f) {
             // sparsity prior: d/da log(1.5 - |0.5 - a|) = sign(0.5 - a) / (1.5 - |0.5 - a|)
             const float d = 0.5f - v.w;
@@ -1121,6 +1128,8 @@ __device__ __forceinline__ void update_block(void* __restrict__ mpi, int D, int 
     }
 }
 
+// the selected planes of a pixel split over 4 thread groups (64 pixels per workgroup)
+constexpr int kUpdateRS = 4;
 template <int DT, bool SHIFT>
 __global__ __launch_bounds__(256) void k_update(void* __restrict__ mpi, int D, int H, int W,
                                                 const uint64_t* __restrict__ mask, int kcap,
@@ -1131,7 +1140,7 @@ __global__ __launch_bounds__(256) void k_update(void* __restrict__ mpi, int D, i
                                                 const float* __restrict__ partials, int64_t nparts,
                                                 double loss_scale, float* __restrict__ out_loss, float prior) {
     extern __shared__ int2 s_off[];   // [nslices][D] (ix, iy) when SHIFT
-    update_block<DT, SHIFT>(mpi, D, H, W, mask, kcap, slots, nslices, warps, cover_w, cover_h, lr_rgb, lr_a,
+    update_block<DT, SHIFT, kUpdateRS>(mpi, D, H, W, mask, kcap, slots, nslices, warps, cover_w, cover_h, lr_rgb, lr_a,
                             do_update, grad_out, partials, nparts, loss_scale, out_loss, prior, blockIdx.x, s_off);
 }
 
@@ -1484,7 +1493,7 @@ int launch_grad_step(const hsgd_mpi& m, const hsgd_views& v, const uint64_t* mas
     const int do_update = (lr_rgb != 0.0f || lr_alpha != 0.0f) ? 1 : 0;
     if (do_update || grad_out || out_loss) {
         ProfScope ps(HSGD_K_UPDATE, s);
-        const dim3 grid((unsigned)ceil_div(HW, 256));
+        const dim3 grid((unsigned)ceil_div(HW, 256 / kUpdateRS));
         const size_t lds = shift ? sizeof(int2) * (size_t)v.N * m.D : 0;
         HSGD_DISPATCH_T(m.dtype, if (shift) {
             hipLaunchKernelGGL((k_update<DT, true>), grid, dim3(256), lds, s, m.rgba, m.D, m.H, m.W, mask, kcap,
