@@ -147,6 +147,9 @@ __device__ __forceinline__ float score_step(float a, float& T) {
 // Top-k: the k largest scores (equal scores: the nearer plane). MVS window: the largest
 // score (equal: the nearer plane) with (k-1)/2 planes before it (rounded down) and the
 // rest after, moved inside [0, D).
+// Every pass below is branch-free: the conditions are combined with bitwise operators
+// and the running best is kept by selects (with short-circuit operators the unrolled
+// passes compiled to a branch per plane).
 template <int MAXD>
 __device__ __forceinline__ uint64_t topk_bits(const float (&A)[MAXD], int D, int k, float tau, int rule) {
     const uint64_t full = D == 64 ? ~0ull : ((1ull << D) - 1);
@@ -158,11 +161,11 @@ __device__ __forceinline__ uint64_t topk_bits(const float (&A)[MAXD], int D, int
         int best = 0;
         float bestA = A[0];
 #pragma unroll
-        for (int z = 1; z < MAXD; ++z)
-            if (z < D && A[z] > bestA) {
-                best = z;
-                bestA = A[z];
-            }
+        for (int z = 1; z < MAXD; ++z) {
+            const bool b = (z < D) & (A[z] > bestA);
+            best = b ? z : best;
+            bestA = b ? A[z] : bestA;
+        }
         const int lo = min(max(best - (kk - 1) / 2, 0), D - kk);
         sel = (kk == 64 ? ~0ull : ((1ull << kk) - 1)) << lo;
     } else if (2 * kk <= D) {
@@ -171,11 +174,11 @@ __device__ __forceinline__ uint64_t topk_bits(const float (&A)[MAXD], int D, int
             int best = -1;
             float bestA = 0.0f;
 #pragma unroll
-            for (int z = 0; z < MAXD; ++z)
-                if (z < D && !((sel >> z) & 1) && (best < 0 || A[z] > bestA)) {
-                    best = z;
-                    bestA = A[z];
-                }
+            for (int z = 0; z < MAXD; ++z) {
+                const bool b = (z < D) & (((sel >> z) & 1ull) == 0ull) & ((best < 0) | (A[z] > bestA));
+                best = b ? z : best;
+                bestA = b ? A[z] : bestA;
+            }
             sel |= 1ull << best;
         }
     } else {
@@ -185,11 +188,11 @@ __device__ __forceinline__ uint64_t topk_bits(const float (&A)[MAXD], int D, int
             int worst = -1;
             float worstA = 0.0f;
 #pragma unroll
-            for (int z = 0; z < MAXD; ++z)
-                if (z < D && !((out >> z) & 1) && (worst < 0 || A[z] <= worstA)) {
-                    worst = z;
-                    worstA = A[z];
-                }
+            for (int z = 0; z < MAXD; ++z) {
+                const bool b = (z < D) & (((out >> z) & 1ull) == 0ull) & ((worst < 0) | (A[z] <= worstA));
+                worst = b ? z : worst;
+                worstA = b ? A[z] : worstA;
+            }
             out |= 1ull << worst;
         }
         sel = full & ~out;
@@ -197,7 +200,7 @@ __device__ __forceinline__ uint64_t topk_bits(const float (&A)[MAXD], int D, int
     if (tau >= 0.0f) {
 #pragma unroll
         for (int z = 0; z < MAXD; ++z)
-            if (z < D && !(A[z] > tau)) sel &= ~(1ull << z);
+            sel &= ~((uint64_t)((z < D) & !(A[z] > tau)) << z);
     }
     return sel;
 }
