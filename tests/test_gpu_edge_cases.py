@@ -1,7 +1,8 @@
 """Degenerate cases of the method on the GPU, each against the FP64 oracle: one plane and one
 view on the smallest frame, a view whose planes all land outside the frame, a mask that
 keeps every plane, the maximum view and plane counts, a single-level refine, a refine with
-no iterations, and the smallest plane-sweep volumes."""
+no iterations, the smallest plane-sweep volumes, and the selection fused into the level
+transition against the stand-alone selection."""
 
 import numpy as np
 import pytest
@@ -165,3 +166,36 @@ def test_refine_with_no_iterations_only_upsamples():
                                    sc.t_views(), sc.depths, (0, 0), sc.k)
     assert losses.numel() == 0
     assert np.abs(out.cpu().numpy() - O.upsample2x(M0)).max() <= 1e-6
+
+
+@pytest.mark.parametrize("D, k, rule, quant, dtype", [
+    (32, 4, "topk", False, torch.float32),
+    (13, 5, "topk", True, torch.float32),       # exact ties in the scores
+    (8, 6, "topk", True, torch.float32),        # k > D/2: the passes that drop the worst
+    (32, 4, "mvs", True, torch.bfloat16),
+    (64, 3, "topk", False, torch.bfloat16),     # every bit of the mask word
+], ids=lambda v: str(v).replace("torch.", ""))
+def test_level_transition_selects_like_select_active(D, k, rule, quant, dtype):
+    """The level transition fuses the 2x upsampling with the new level's first selection. A
+    two-level refine that spends its only iteration on the finer level must equal, bit for
+    bit, the upsampling, hsgd_select_active on the stored level and one hsgd_grad_step on
+    that mask with the same rates (quantised alphas put exact ties into the scores)."""
+    W, H, N, f = 64, 32, 3, 40.0
+    rng = np.random.default_rng(80 + D)
+    rg = shift_rig(W, H, D, f, rng.uniform(-0.05, 0.05, size=(N, 2)))
+    M0 = rng.uniform(0.05, 0.95, size=(D, H // 2, W // 2, 4))
+    if quant:
+        M0[..., 3] = rng.integers(0, 5, size=(D, H // 2, W // 2)) / 4.0
+    M0d = to_dev(M0, dtype)
+    I = to_dev(rng.uniform(size=(N, H, W, 3)))
+    lr_rgb, lr_a = 0.7, 0.9
+    print(f"level transition D={D} k={k} rule={rule} {dtype}", flush=True)
+    out, losses = hsgd.hsgd_refine(M0d, I, rg["K_ref"], rg["K"], rg["R"], rg["t"], rg["depths"], (0, 1), k,
+                                   lr_rgb=lr_rgb, lr_alpha=lr_a, rule=rule)
+    up = hsgd.hsgd_upsample2x(M0d)
+    mask = hsgd.hsgd_select_active(up, k, rule=rule, with_ids=False)
+    _, loss = hsgd.hsgd_grad_step(up, device_warps(hsgd, rg), N, images=I, mask=mask, kcap=k, lr_rgb=lr_rgb,
+                                  lr_alpha=lr_a, want_loss=True)
+    torch.cuda.synchronize()
+    assert torch.equal(out, up)
+    assert losses.numel() == 1 and abs(losses.item() - loss.item()) <= 1e-6 * loss.item()
