@@ -9,6 +9,10 @@
     python -m paper_2307_03017_amd.profiling traffic --fetch <fetch counter_collection.csv> \\
         --write <write counter_collection.csv> --kernel k_grad_shift --copy-bytes 268435456 \\
         --cmd "<commands>" --json out.json --md out.md
+
+    # instruction mix and issue-slot load per launch size (rocprofv3 --pmc of SQ_COUNTERS)
+    python -m paper_2307_03017_amd.profiling sq <counter_collection.csv> --agent <agent_info.csv> \
+        --kernel k_grad_shift --cmd "<commands>" --json out.json --md out.md
 """
 
 from __future__ import annotations
@@ -178,6 +182,63 @@ def l2_md(t, cmd: str) -> str:
     return "\n".join(out) + "\n"
 
 
+SQ_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_WAVES", "SQ_WAVE_CYCLES",
+               "SQ_ACTIVE_INST_VALU", "SQ_WAIT_INST_ANY", "SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE")
+
+
+def sq(csv_path: str, agent_csv: str, kernel: str):
+    """Instruction mix and issue load of one kernel per launch size, from a rocprofv3 --pmc run
+    of SQ_COUNTERS. A wave64 VALU (or SALU) instruction holds its SIMD's issue slot of that
+    type for 4 cycles; GRBM_GUI_ACTIVE sums the busy cycles of every XCD, so a launch lasts
+    GRBM_GUI_ACTIVE / XCDs cycles and the slot load is 4 * instructions / (SIMDs * cycles)."""
+    gpu = [r for r in csv.DictReader(open(agent_csv)) if int(r.get("Simd_Count") or 0) > 0][0]
+    simds, xcds = int(gpu["Simd_Count"]), int(gpu["Num_Xcc"])
+    per = defaultdict(dict)
+    for r in csv.DictReader(open(csv_path)):
+        if short_name(r["Kernel_Name"]).split("<")[0] != kernel:
+            continue
+        d = per[r["Dispatch_Id"]]
+        d[r["Counter_Name"]] = float(r["Counter_Value"])
+        d["name"] = short_name(r["Kernel_Name"])
+        d["grid"] = int(r["Grid_Size"])
+        d["dur"] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    groups = defaultdict(list)
+    for d in per.values():
+        groups[(d["name"], d["grid"])].append(d)
+    out = []
+    for (name, grid), ds in sorted(groups.items(), key=lambda kv: kv[0][1]):
+        m = {c: sum(d[c] for d in ds) / len(ds) for c in SQ_COUNTERS + ("dur",)}
+        cyc = m["GRBM_GUI_ACTIVE"] / xcds
+        out.append(dict(kernel=name, grid=grid, launches=len(ds), us=m["dur"] * 1e6,
+                        clock_ghz=cyc / m["dur"] / 1e9, waves=m["SQ_WAVES"],
+                        valu_per_wave=m["SQ_INSTS_VALU"] / m["SQ_WAVES"],
+                        salu_per_wave=m["SQ_INSTS_SALU"] / m["SQ_WAVES"],
+                        lds_per_wave=m["SQ_INSTS_LDS"] / m["SQ_WAVES"],
+                        valu_slot_load=4 * m["SQ_INSTS_VALU"] / (simds * cyc),
+                        salu_slot_load=4 * m["SQ_INSTS_SALU"] / (simds * cyc),
+                        wait_share=m["SQ_WAIT_INST_ANY"] / m["SQ_WAVE_CYCLES"]))
+    return dict(kernel=kernel, simds=simds, xcds=xcds, rows=out, kernel_source_hash=kernel_source_hash(kernel))
+
+
+def sq_md(t, cmd: str) -> str:
+    out = [f"# Instruction mix and issue load: `{t['kernel']}`", "", "Command:", "", "```", cmd, "```", "",
+           f"Kernel source hash: `{t['kernel_source_hash']}`", "",
+           f"{t['simds']} SIMDs in {t['xcds']} XCDs. A wave64 VALU or SALU instruction holds its SIMD's "
+           "issue slot of that type for 4 cycles; a launch lasts GRBM_GUI_ACTIVE / XCDs cycles (the "
+           "clock column is those cycles over the launch's timestamps). Slot load = 4 x instructions / "
+           "(SIMDs x cycles); waiting = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES (share of wave time spent "
+           "waiting for a dependency before the next instruction could issue).", "",
+           "| kernel | grid | launches | us | clock GHz | waves | VALU / wave | SALU / wave | LDS / wave "
+           "| VALU slot load | SALU slot load | waiting |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for r in t["rows"]:
+        out.append(f"| `{r['kernel']}` | {r['grid']} | {r['launches']} | {r['us']:.1f} | {r['clock_ghz']:.2f} "
+                   f"| {r['waves']:.0f} | {r['valu_per_wave']:.0f} | {r['salu_per_wave']:.0f} "
+                   f"| {r['lds_per_wave']:.0f} | {100 * r['valu_slot_load']:.1f}% | {100 * r['salu_slot_load']:.1f}% "
+                   f"| {100 * r['wait_share']:.1f}% |")
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd_name", required=True)
@@ -198,7 +259,23 @@ def main(argv=None):
     c.add_argument("--cmd", default="")
     c.add_argument("--json")
     c.add_argument("--md")
+    e = sub.add_parser("sq")
+    e.add_argument("csv")
+    e.add_argument("--agent", required=True, help="the run's agent_info.csv")
+    e.add_argument("--kernel", default="k_grad_shift")
+    e.add_argument("--cmd", default="")
+    e.add_argument("--json")
+    e.add_argument("--md")
     args = ap.parse_args(argv)
+    if args.cmd_name == "sq":
+        t = sq(args.csv, args.agent, args.kernel)
+        if args.json:
+            json.dump(t, open(args.json, "w"), indent=1)
+        md = sq_md(t, args.cmd)
+        if args.md:
+            open(args.md, "w").write(md)
+        print(md)
+        return
     if args.cmd_name == "l2":
         t = l2(args.csv)
         if args.json:
