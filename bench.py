@@ -91,14 +91,18 @@ def grad_launch_flops(D, shapes, iters, N, k):
 
 def refine_alg_bytes(D, shapes, iters, N, k, s):
     """Algorithmic bytes of a whole refine (the method's minimum traffic): per level the
-    coarse MPI read and the upsampled MPI written (l > 0); per iteration one dense MPI read,
-    the FP32 targets and the read-modify-write of the active voxels with their int32 ids."""
+    MPI it starts from read once (the initial MPI at the coarsest level, the coarser level's
+    result above it) and, above the coarsest, the upsampled MPI written; per iteration one
+    dense MPI read, the FP32 targets and the read-modify-write of the active voxels with
+    their int32 ids. 512x384x32 with 4 views in FP32: 345.24 MB."""
     total = 0
     for l, ((w, h), n) in enumerate(zip(shapes, iters)):
         HW = w * h
         if l > 0:
             pw, ph = shapes[l - 1]
             total += D * pw * ph * s + D * HW * s
+        else:
+            total += D * HW * s
         total += n * (D * HW * s + N * HW * 12 + k * HW * (4 + 2 * s))
     return total
 

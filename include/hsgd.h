@@ -363,7 +363,10 @@ hsgd_status hsgd_batch_admit(hsgd_batch* b, const hsgd_request* r, int64_t* tick
 
 /* Enqueues one iteration of every admitted request on stream (one table upload, one
  * graph launch). Blocks the host only while the step before the previous one still holds
- * its staging buffer. Outputs (each may be NULL): *n_active requests stepped; the tickets
+ * its staging buffer. Steps run in the order they are enqueued whatever streams they are
+ * given: a step enqueued on a stream other than the previous step's first makes that
+ * stream wait for the previous step to complete (all steps share one device table, and
+ * each continues the requests of the one before). Outputs (each may be NULL): *n_active requests stepped; the tickets
  * of requests whose last iteration this step holds, up to max_finished of them, and their
  * number *n_finished. With no request in flight it enqueues nothing. */
 hsgd_status hsgd_batch_step(hsgd_batch* b, hipStream_t stream, int32_t* n_active,

@@ -113,6 +113,7 @@ struct hsgd_batch {
     bool have_ref = false;
     hipGraphExec_t exec = nullptr;
     hipStream_t capture = nullptr;                    // private stream the graph is captured on
+    hipStream_t last_stream = nullptr;                // stream of the latest step (valid once steps > 0)
     int64_t steps = 0;
     std::vector<Slot> slots;
     std::vector<Ticket> tickets;
@@ -388,6 +389,12 @@ hsgd_status hsgd_batch_step(hsgd_batch* b, hipStream_t stream, int32_t* n_active
     // the ring entry about to be reused: keep its completion time
     const int64_t old = b->steps - kRing;
     if (old >= 0) b->harvest(old);
+    // Every step rewrites the one device table and continues the requests of the step
+    // before it: on a stream other than that step's, wait for that step to finish first.
+    if (b->steps > 0 && stream != b->last_stream) {
+        e = hipStreamWaitEvent(stream, b->step_ev[(int)((b->steps - 1) % kRing)], 0);
+        if (e != hipSuccess) return hip_status(e, fn);
+    }
     fill_table(b, b->staging[cur], order);
     e = hipMemcpyAsync(b->dev_table, b->staging[cur], sizeof(BatchTable), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipEventRecord(b->copy_done[cur], stream);
@@ -414,6 +421,7 @@ hsgd_status hsgd_batch_step(hsgd_batch* b, hipStream_t stream, int32_t* n_active
     if (e == hipSuccess) e = hipEventRecord(b->step_ev[ri], stream);
     if (e != hipSuccess) return hip_status(e, fn);
     b->step_harvested[ri] = false;
+    b->last_stream = stream;
 
     int nf = 0;
     for (int si : order) {

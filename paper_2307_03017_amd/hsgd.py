@@ -183,6 +183,19 @@ def _f32(t: torch.Tensor | None, what: str):
         raise TypeError(f"{what} must be float32")
 
 
+def _check_mask(mask: torch.Tensor | None, m: "Mpi", device):
+    """A plane mask is int64 [H][W] (one 64-bit word per pixel), contiguous, on the MPI's
+    device: the select kernel writes H x W words into it and the gradient kernels read them."""
+    if mask is None:
+        return
+    if mask.dtype != torch.int64 or tuple(mask.shape) != (m.H, m.W):
+        raise ValueError(f"mask must be int64 [{m.H}][{m.W}]")
+    if mask.device != torch.device(device):
+        raise ValueError(f"mask is on device {mask.device}, the MPI on device {device}")
+    if not mask.is_contiguous():
+        raise ValueError("mask must be contiguous")
+
+
 # ---------------------------------------------------------------------------------------
 # descriptors
 # ---------------------------------------------------------------------------------------
@@ -216,18 +229,31 @@ class WarpTable:
         return bool(self.flags & HSGD_VIEWS_SHIFT_ONLY)
 
 
-def views_desc(warps, N: int, H: int, W: int, images: torch.Tensor | None = None) -> Views:
+def views_desc(warps, N: int, H: int, W: int, images: torch.Tensor | None = None, D: int | None = None,
+               device=None) -> Views:
     """warps: a WarpTable, or a raw device tensor of hsgd_warp records (then the general
-    warp path is used even for translations)."""
+    warp path is used even for translations). The kernels read record [view][plane] of a
+    table laid out [N][D], so the table must hold N x D records for the MPI's D planes (a
+    WarpTable: exactly D planes and at least N views). device: the MPI's device, which the
+    table and the images must share."""
     flags = 0
     if isinstance(warps, WarpTable):
+        if D is not None and warps.D != D:
+            raise ValueError(f"warp table has {warps.D} planes, the MPI {D}")
+        if warps.N < N:
+            raise ValueError(f"warp table has {warps.N} views, {N} requested")
         flags = warps.flags
         warps = warps.tensor
+    need = N * (1 if D is None else D) * 64
+    if warps.numel() * warps.element_size() < need:
+        raise ValueError(f"warp table holds fewer than N x D = {need // 64} records")
     _dev(warps, "warps")
     _dev(images, "images")
     _f32(images, "images")
-    if warps.numel() < N * 64:
-        raise ValueError("warp table holds fewer than N records")
+    if device is not None:
+        for t, what in ((warps, "warps"), (images, "images")):
+            if t is not None and t.device != torch.device(device):
+                raise ValueError(f"{what} are on device {t.device}, the MPI on device {device}")
     if images is not None and tuple(images.shape) != (N, H, W, 3):
         raise ValueError(f"images must be [{N}][{H}][{W}][3]")
     return Views(_ptr(images), _ptr(warps), N, H, W, flags)
@@ -307,6 +333,7 @@ def hsgd_select_active(rgba: torch.Tensor, k: int, tau: float = -1.0, with_ids: 
     dev = rgba.device
     if mask is None:
         mask = torch.empty((m.H, m.W), dtype=torch.int64, device=dev)
+    _check_mask(mask, m, dev)
     ids = plane_off = n_active = ws = None
     cap = 0
     if with_ids:
@@ -327,7 +354,7 @@ def hsgd_render(rgba: torch.Tensor, warps: torch.Tensor, N: int, images: torch.T
                 want_rgb: bool = True, want_loss: bool = False, stream=None):
     """Render N views ([N][H][W][3] float32) and/or the photometric loss against images."""
     m = mpi_desc(rgba)
-    v = views_desc(warps, N, m.H, m.W, images)
+    v = views_desc(warps, N, m.H, m.W, images, D=m.D, device=rgba.device)
     dev = rgba.device
     out = torch.empty((N, m.H, m.W, 3), dtype=torch.float32, device=dev) if want_rgb else None
     loss = torch.empty(1, dtype=torch.float32, device=dev) if want_loss else None
@@ -346,14 +373,15 @@ def hsgd_grad_step(rgba: torch.Tensor, warps: torch.Tensor, N: int, images: torc
     the sparsity prior lambda_s L_s added to the gradient when lambda_s != 0.
     Returns (grad [D][H][W][4] float32 or None, loss [1] or None)."""
     m = mpi_desc(rgba)
-    v = views_desc(warps, N, m.H, m.W, images)
+    v = views_desc(warps, N, m.H, m.W, images, D=m.D, device=rgba.device)
     _dev(mask, "mask")
     _dev(dimg, "dimg")
     _f32(dimg, "dimg")
     if dimg is not None and tuple(dimg.shape) != (N, m.H, m.W, 3):
         raise ValueError("dimg must be [N][H][W][3]")
-    if mask is not None and (mask.dtype != torch.int64 or tuple(mask.shape) != (m.H, m.W)):
-        raise ValueError("mask must be int64 [H][W]")
+    _check_mask(mask, m, rgba.device)
+    if dimg is not None and dimg.device != rgba.device:
+        raise ValueError("dimg must be on the MPI's device")
     kc = m.D if mask is None else (kcap if kcap is not None else m.D)
     dev = rgba.device
     grad = torch.empty((m.D, m.H, m.W, 4), dtype=torch.float32, device=dev) if want_grad else None
@@ -403,7 +431,7 @@ def hsgd_plane_sweep(images: torch.Tensor, warps, D: int, L: int = 1, store=None
             raise ValueError(f"warp table is {warps.N} x {warps.D}, expected {N} x {D}")
     elif warps.numel() < N * D * 64:
         raise ValueError("warp table holds fewer than N * D records")
-    v = views_desc(warps, N, H, W, images)
+    v = views_desc(warps, N, H, W, images, D=D, device=images.device)
     store = [True] * L if store is None else list(store)
     if len(store) != L:
         raise ValueError("store needs one entry per level")
@@ -494,7 +522,7 @@ class RefinePlan:
         vs = []
         for l, (w, h) in enumerate(self.shapes):
             img = images if l == self.L - 1 else (coarse_images[l] if coarse_images else None)
-            vs.append(views_desc(self.warps[l], self.N, h, w, img))
+            vs.append(views_desc(self.warps[l], self.N, h, w, img, D=self.D))
         return mpis, (Views * self.L)(*vs)
 
     def run(self, images: torch.Tensor, descriptors=None, stream=None):
@@ -547,7 +575,7 @@ class ServingStream:
         req.L = L
         for l, (w, h) in enumerate(self.shapes):
             req.levels[l] = mpi_desc(self.levels[l])
-            req.views[l] = views_desc(self.warps[l], self.N, h, w, self.images[l])
+            req.views[l] = views_desc(self.warps[l], self.N, h, w, self.images[l], D=self.D)
             req.iters[l] = self.iters[l]
         req.sel = select_params(self.k, tau, rule)
         req.lr_rgb, req.lr_alpha, req.lambda_s = float(lr_rgb), float(lr_alpha), float(lambda_s)

@@ -77,3 +77,61 @@ def patch_render(O, M, G, i, rows, cols):
     """Oracle render of view i's pixels rows x cols (inclusive ranges) of the full frame."""
     Mc, Gc, _ = _crop_problem(M, G[i], rows, cols)
     return O.render_view(Mc, Gc)[0][:rows[1] - rows[0] + 1, :cols[1] - cols[0] + 1]
+
+
+def grad_voxels(O, M, G, targets, vox):
+    """The oracle's dL/dM (all 4 channels) at the voxels vox = [(z, Y, X), ...] of a full
+    frame with translation maps, as an array [len(vox)][4].
+
+    For view i, voxel (z, Y, X) is read only by the view rays of the 2x2 patch whose taps on
+    plane z cover it. Every voxel gets a slot in one mosaic MPI: the 4x4 view pixels around
+    its patch and, on every plane, their tap window (zero outside the frame). All crops of
+    view i share one map per plane (same fractional shift, the integer part absorbed into
+    the crop origin), so the oracle renders the mosaic once and back-propagates the
+    photometric residual (C - I) / N of the slots' in-frame pixels with its own render_vjp
+    (the residual is 0 on every other mosaic pixel). A voxel's value is the mosaic gradient
+    at its slot position, summed over the views."""
+    M = np.asarray(M)
+    D, H, W, _ = M.shape
+    N = len(G)
+    hw = 2 * MARGIN                  # patch side (view pixels)
+    cs = hw + 2 * PAD                # crop side (MPI pixels); crop pixel (MARGIN + PAD)^2 is the voxel
+    slot = cs                        # slots side by side (their other rays carry no residual)
+    n = len(vox)
+    out = np.zeros((n, 4))
+    for i in range(N):
+        sx, sy = G[i, :, 0, 2], G[i, :, 1, 2]
+        ix, iy = np.floor(sx).astype(int), np.floor(sy).astype(int)
+        Gc = np.repeat(np.eye(3)[None], D, axis=0)
+        Gc[:, 0, 2] = sx - ix + PAD
+        Gc[:, 1, 2] = sy - iy + PAD
+        zv = np.array([v[0] for v in vox])
+        Yv = np.array([v[1] for v in vox])
+        Xv = np.array([v[2] for v in vox])
+        r0, c0 = Yv - iy[zv] - MARGIN, Xv - ix[zv] - MARGIN     # patch origins (view pixels)
+        Mc = np.zeros((D, cs, n, slot, 4))
+        j = np.arange(cs)
+        for z in range(D):
+            ry = (r0 + iy[z] - PAD)[:, None] + j[None]          # [n][cs] plane rows of the crops
+            rx = (c0 + ix[z] - PAD)[:, None] + j[None]
+            ok = ((ry >= 0) & (ry < H))[:, :, None] & ((rx >= 0) & (rx < W))[:, None, :]
+            blk = M[z][np.clip(ry, 0, H - 1)[:, :, None], np.clip(rx, 0, W - 1)[:, None, :]]
+            Mc[z, :, :, :cs] = np.where(ok[..., None], blk, 0.0).transpose(1, 0, 2, 3)
+        Mc = Mc.reshape(D, cs, n * slot, 4)
+        T = np.zeros((cs, n, slot, 3))
+        valid = np.zeros((cs, n, slot), bool)
+        j = np.arange(hw)
+        py = r0[:, None] + j[None]                               # [n][hw] view rows / columns
+        px = c0[:, None] + j[None]
+        inside = ((py >= 0) & (py < H))[:, :, None] & ((px >= 0) & (px < W))[:, None, :]
+        tv = targets[i][np.clip(py, 0, H - 1)[:, :, None], np.clip(px, 0, W - 1)[:, None, :]]
+        valid[:hw, :, :hw] = inside.transpose(1, 0, 2)
+        T[:hw, :, :hw] = np.where(inside[..., None], tv, 0.0).transpose(1, 0, 2, 3)
+        T = T.reshape(cs, n * slot, 3)
+        valid = valid.reshape(cs, n * slot)
+        C = O.render(Mc, Gc[None])[0]
+        r = np.where(valid[..., None], (C - T) / N, 0.0)
+        g = O.render_vjp(Mc, Gc[None], r[None])
+        for k, (z0, Y, X) in enumerate(vox):
+            out[k] += g[z0, MARGIN + PAD, k * slot + MARGIN + PAD]
+    return out

@@ -65,3 +65,27 @@ def rel_err(a, b):
     b = np.asarray(b, np.float64)
     den = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
+
+
+def grad_close(g, g_ref, rtol, what=""):
+    """The gradient parity bound at relative tolerance rtol: over the compared set
+    ||g - g_ref|| / ||g_ref|| <= rtol, and for every element
+    |g - g_ref| <= rtol |g_ref| + 0.01 rtol max|g_ref| (rtol 1e-4: 1e-4 |g_ref| + 1e-6 max|g_ref|).
+    The elementwise form catches an error confined to a few cells (a tile seam, a frame
+    border) that the global norm would dilute. Returns (norm ratio, worst elementwise ratio)
+    and prints both."""
+    a = np.asarray(g, np.float64).ravel()
+    b = np.asarray(g_ref, np.float64).ravel()
+    assert a.shape == b.shape, (a.shape, b.shape)
+    rel = rel_err(a, b)
+    bound = rtol * np.abs(b) + 0.01 * rtol * (np.abs(b).max() if b.size else 0.0)
+    d = np.abs(a - b)
+    worst = float((d / np.where(bound > 0, bound, 1.0)).max()) if b.size else 0.0
+    print(f"{what} gradient: norm ratio {rel:.2e} (tol {rtol:.0e}), worst elementwise {worst:.3f} of the bound",
+          flush=True)
+    assert rel <= rtol, (what, rel)
+    if not np.all(d <= bound):
+        i = int(np.argmax(d - bound))
+        raise AssertionError(f"{what}: element {i} differs by {d[i]:.3e} > bound {bound[i]:.3e} "
+                             f"(g {a[i]:.6e}, ref {b[i]:.6e}); {int(np.sum(d > bound))} of {d.size} beyond")
+    return rel, worst

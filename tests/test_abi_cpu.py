@@ -268,3 +268,38 @@ def test_batch_calls_reject_null_handles():
     out = ctypes.c_void_p()
     bad = hsgd.BatchConfig(0, 32, 5, 756, 1008, 4, hsgd.HSGD_BF16, 0, 1 << 36)
     assert L.hsgd_batch_create(ctypes.byref(bad), FAKE, 1 << 30, ctypes.byref(out)) == -1
+
+
+def test_binding_rejects_warp_tables_and_masks_that_do_not_fit():
+    """The kernels read warp record [view][plane] of an [N][D] table and write H x W mask
+    words, which the C ABI cannot check against the buffers' sizes: the binding refuses a
+    table built for fewer planes or views than the call uses, and a mask of the wrong
+    dtype, shape or device, before anything is launched."""
+    rg = rig(3, 2, 8, 16, 12, 20.0, 0.05)
+    raw = hsgd.hsgd_build_warps(rg["K_ref"], rg["K"], rg["R"], rg["t"], rg["depths"])   # N=2, D=8
+    table = hsgd.WarpTable(raw, device="cpu")
+    with pytest.raises(ValueError, match="planes"):
+        hsgd.views_desc(table, 2, 12, 16, D=16)
+    with pytest.raises(ValueError, match="views"):
+        hsgd.views_desc(table, 3, 12, 16, D=8)
+    import torch
+    tens = torch.from_numpy(raw.reshape(-1))
+    with pytest.raises(ValueError, match="N x D"):
+        hsgd.views_desc(tens, 2, 12, 16, D=9)
+    with pytest.raises(ValueError, match="N x D"):
+        hsgd.views_desc(tens[: 2 * 8 * 64 - 1], 2, 12, 16, D=8)
+    # a table that fits gets as far as the device check (these tensors live on the host)
+    with pytest.raises(ValueError, match="device tensor"):
+        hsgd.views_desc(table, 2, 12, 16, D=8)
+    m = hsgd.Mpi(FAKE, 8, 12, 16, hsgd.HSGD_FP32)
+    hsgd._check_mask(None, m, "cuda")
+    with pytest.raises(ValueError, match="int64"):
+        hsgd._check_mask(torch.zeros((12, 16), dtype=torch.int32), m, "cpu")
+    with pytest.raises(ValueError, match="int64"):
+        hsgd._check_mask(torch.zeros((16, 12), dtype=torch.int64), m, "cpu")
+    with pytest.raises(ValueError, match="device"):
+        hsgd._check_mask(torch.zeros((12, 16), dtype=torch.int64), m, "cuda")
+    with pytest.raises(ValueError, match="contiguous"):
+        hsgd._check_mask(torch.zeros((16, 12), dtype=torch.int64).t(), m, "cpu")
+    hsgd._check_mask(torch.zeros((12, 16), dtype=torch.int64), m, "cpu")
+

@@ -11,7 +11,7 @@ import torch
 from oracle import hsgd_oracle as O
 from paper_2307_03017_amd import autograd, hsgd, scenes
 from tests._crop_fd import fd_scalar
-from tests._problems import f32, mask_bits, rel_err
+from tests._problems import f32, grad_close, mask_bits, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -57,8 +57,7 @@ def test_autograd_matches_finite_differences_full_frame(frame, storage):
             ref.append(fd_scalar(O, Mq, G, targets, (int(z), int(y), int(x), ch)))
             got.append(grad[z, y, x, ch])
     got, ref = np.array(got), np.array(ref)
-    assert rel_err(got, ref) <= 1e-4
-    assert np.mean(np.abs(got - ref) <= 1e-4 * np.abs(ref) + 1e-6 * np.abs(ref).max()) > 0.98
+    grad_close(got, ref, 1e-4, f"autograd {storage}")
 
 
 def test_photometric_loss_function_equals_render_path(frame):

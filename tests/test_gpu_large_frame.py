@@ -4,8 +4,11 @@ the launch configuration of the large-frame refine, checked at full size.
 The oracle cannot render this frame whole in test time, so the checks are
 * the active set: every plane mask word and every id, against the oracle's FP32 select
   over the whole frame (bit-exact);
-* the restricted gradient: zero off S everywhere; on 48 random active voxels x 4 channels,
-  the oracle's exact derivative (central differences of a quadratic, on per-view crops);
+* the restricted gradient: zero off S everywhere; on 512 active voxels x 4 channels the
+  oracle's exact gradient (its render and VJP on per-view crop mosaics), elementwise: half of
+  the voxels random, half on the gradient kernel's owner-tile seams (cells whose owner ray
+  sits in a tile's first or last owner column or row for some view) and on the frame
+  borders, including the cells owned past the frame's last column or row;
 * the update: every voxel off S unchanged; on the sampled voxels, the oracle's BF16 update;
 * the render: sampled patches of every view against the oracle's patch renders;
 * the loss: the full-frame reduction equals the FP64 sum over the GPU's own render;
@@ -21,8 +24,11 @@ import torch
 
 from oracle import hsgd_oracle as O
 from paper_2307_03017_amd import hsgd, scenes
-from tests._crop_fd import fd_scalar, patch_render
-from tests._problems import mask_bits
+import os
+import re
+
+from tests._crop_fd import grad_voxels, patch_render
+from tests._problems import grad_close, mask_bits
 
 pytestmark = pytest.mark.gpu
 
@@ -71,22 +77,60 @@ def _sample_active(S, n, seed):
     return act[rng.choice(len(act), n, replace=False)]
 
 
+def _owner_tile():
+    """Owner columns and rows per tile of the translation gradient kernel (the kernel's own
+    constants): the owner ray x of tile t runs over [t OX, t OX + OX)."""
+    src = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                            "paper_2307_03017_amd", "csrc", "hsgd_internal.h")).read()
+    ox = int(re.search(r"constexpr int kShiftOX = (\d+);", src).group(1))
+    oy = int(re.search(r"constexpr int kShiftOY = (\d+);", src).group(1))
+    return ox, oy
+
+
+def _seam_and_border_voxels(S, G, n, seed):
+    """Active voxels on the owner-tile seams of some view (owner ray in the first or last
+    owner column or row of its tile), on the frame border, and owned past the frame (the
+    cell right of / below the last ray of a view), n of them, drawn in equal parts."""
+    rng = np.random.default_rng(seed)
+    D, H, W = S.shape
+    OX, OY = _owner_tile()
+    act = np.argwhere(S)
+    z, Y, X = act[:, 0], act[:, 1], act[:, 2]
+    N = len(G)
+    ix = np.floor(G[:, :, 0, 2]).astype(int)          # [N][D]
+    iy = np.floor(G[:, :, 1, 2]).astype(int)
+    xs = X[None] - ix[:, z]                           # owner ray of each view
+    ys = Y[None] - iy[:, z]
+    col_seam = np.any(((xs % OX == 0) | (xs % OX == OX - 1)) & (xs >= 0) & (xs <= W), axis=0)
+    row_seam = np.any(((ys % OY == 0) | (ys % OY == OY - 1)) & (ys >= 0) & (ys <= H), axis=0)
+    past = np.any((xs == W) | (ys == H), axis=0)
+    border = (X == 0) | (X == W - 1) | (Y == 0) | (Y == H - 1)
+    groups = [np.flatnonzero(col_seam & row_seam), np.flatnonzero(col_seam & ~row_seam),
+              np.flatnonzero(border), np.flatnonzero(past)]
+    per = n // len(groups)
+    pick = []
+    for g in groups:
+        assert len(g) >= per, (len(g), per)
+        pick.append(g[rng.choice(len(g), per, replace=False)])
+    return act[np.concatenate(pick)]
+
+
 def test_large_frame_restricted_gradient_and_update(frame):
     sc, Md, S, Mq, I, G = frame["sc"], frame["Md"], frame["S"], frame["Mq"], frame["I"], frame["G"]
     mask = hsgd.hsgd_select_active(Md, sc.k, with_ids=False)
     g, _ = hsgd.hsgd_grad_step(Md, frame["table"], sc.N, images=frame["Id"], mask=mask, kcap=sc.k,
                                want_grad=True)
-    pick = _sample_active(S, 48, 3)
+    pick = np.concatenate([_sample_active(S, 256, 3), _seam_and_border_voxels(S, G, 256, 4)])
     pz, py, px = (torch.from_numpy(pick[:, i]).to(DEV) for i in range(3))
-    got = g[pz, py, px].cpu().numpy().astype(np.float64)                  # [48][4]
+    got = g[pz, py, px].cpu().numpy().astype(np.float64)                  # [512][4]
     gh = g.cpu().numpy()
     del g
     assert not np.any(gh[~S])
     del gh
-    ref = np.array([[fd_scalar(O, Mq, G, I, (int(z), int(y), int(x), ch)) for ch in range(4)]
-                    for z, y, x in pick])
-    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-    assert err <= 1e-4, err
+    ref = grad_voxels(O, Mq, G, I, [tuple(int(v) for v in p) for p in pick])
+    grad_close(got[:256], ref[:256], 1e-4, "1920x1080x64 random voxels")
+    grad_close(got[256:], ref[256:], 1e-4, "1920x1080x64 seam and border voxels")
+    grad_close(got, ref, 1e-4, "1920x1080x64 all sampled voxels")
     # the update from the same state: off S untouched, on the samples the oracle's BF16 step
     lr = 1.0
     M2 = Md.clone()

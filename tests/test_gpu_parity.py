@@ -12,7 +12,7 @@ import torch
 
 from oracle import hsgd_oracle as O
 from paper_2307_03017_amd import hsgd, scenes
-from tests._problems import device_warps, f32, mask_bits, oracle_maps, rel_err, rig
+from tests._problems import device_warps, f32, grad_close, mask_bits, oracle_maps, rel_err, rig
 
 pytestmark = pytest.mark.gpu
 
@@ -164,7 +164,7 @@ def test_dense_gradient_matches_oracle(case):
     g, loss = hsgd.hsgd_grad_step(to_dev(M), device_warps(hsgd, rg), N, images=to_dev(I),
                                   want_grad=True, want_loss=True)
     torch.cuda.synchronize()
-    assert rel_err(g.cpu().numpy(), g_ref) <= rtol
+    grad_close(g.cpu().numpy(), g_ref, rtol, f"dense seed {seed}")
     assert abs(loss.item() - L_ref) <= 1e-5 * L_ref
 
 
@@ -184,7 +184,7 @@ def test_sparse_gradient_is_masked_dense_gradient(case):
     assert np.array_equal(S, O.select_active(M[..., 3], k))
     g = g.cpu().numpy()
     assert np.all(g[~S] == 0.0)
-    assert rel_err(g[S], g_ref[S]) <= rtol
+    grad_close(g[S], g_ref[S], rtol, f"restricted seed {seed}")
 
 
 @pytest.mark.parametrize("general", [False, True], ids=["shift", "general"])
@@ -200,7 +200,7 @@ def test_bf16_storage_gradient_matches_oracle(general):
     assert table.shift_only == (not general)
     g, loss = hsgd.hsgd_grad_step(Md, table, N, images=to_dev(I), want_grad=True, want_loss=True)
     rtol = 1e-3 if general else GRAD_RTOL
-    assert rel_err(g.cpu().numpy(), g_ref) <= rtol
+    grad_close(g.cpu().numpy(), g_ref, rtol, "BF16 dense")
     assert abs(loss.item() - L_ref) <= (1e-4 if general else 1e-5) * L_ref
     k = 3
     mask = hsgd.hsgd_select_active(Md, k, with_ids=False)
@@ -209,7 +209,7 @@ def test_bf16_storage_gradient_matches_oracle(general):
     assert np.array_equal(S, O.select_active(Mq[..., 3], k))
     gs = gs.cpu().numpy()
     assert np.all(gs[~S] == 0.0)
-    assert rel_err(gs[S], g_ref[S]) <= rtol
+    grad_close(gs[S], g_ref[S], rtol, "BF16 restricted")
 
 
 def test_vjp_matches_oracle():
@@ -218,7 +218,7 @@ def test_vjp_matches_oracle():
     gimg = f32(rng.normal(size=(3, 41, 77, 3)))
     ref = O.render_vjp(M, oracle_maps(O, rg), gimg)
     g, _ = hsgd.hsgd_grad_step(to_dev(M), device_warps(hsgd, rg), 3, dimg=to_dev(gimg), want_grad=True)
-    assert rel_err(g.cpu().numpy(), ref) <= GRAD_RTOL
+    grad_close(g.cpu().numpy(), ref, GRAD_RTOL, "VJP")
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16], ids=["fp32", "bf16"])
@@ -373,7 +373,7 @@ def test_full_size_select_and_gradient_c2():
                                   want_grad=True, want_loss=True)
     g = g.cpu().numpy()
     assert np.all(g[~S] == 0.0)
-    assert rel_err(g[S], g_ref[S]) <= GRAD_RTOL
+    grad_close(g[S], g_ref[S], GRAD_RTOL, "512x384x32 restricted")
     assert abs(loss.item() - L_ref) <= 1e-5 * L_ref
 
 
@@ -405,7 +405,7 @@ def test_shift_path_large_shifts_and_borders():
     rg, M, I = problem(60, N, D, W, H, 400.0, 0.1, lo=0.05, hi=0.95)   # up to 40 px
     _, g_ref = O.loss_and_grad(M, oracle_maps(O, rg), I)
     g, _ = hsgd.hsgd_grad_step(to_dev(M), device_warps(hsgd, rg), N, images=to_dev(I), want_grad=True)
-    assert rel_err(g.cpu().numpy(), g_ref) <= GRAD_RTOL
+    grad_close(g.cpu().numpy(), g_ref, GRAD_RTOL, "large shifts")
 
 
 # --------------------------------------------------------------------------------- sparsity prior
@@ -428,7 +428,7 @@ def test_update_step_with_sparsity_prior(dtype):
                                want_grad=True, lambda_s=lam)
     g = g.cpu().numpy()
     assert np.all(g[~S] == 0.0)
-    assert rel_err(g[S], g_ref[S]) <= GRAD_RTOL
+    grad_close(g[S], g_ref[S], GRAD_RTOL, "with prior")
     hsgd.hsgd_grad_step(Md, device_warps(hsgd, rg), 3, images=to_dev(I), mask=mask, kcap=k,
                         lr_rgb=lr, lr_alpha=lr, lambda_s=lam)
     got = Md.float().cpu().numpy()
@@ -456,3 +456,84 @@ def test_refine_with_sparsity_prior_matches_oracle():
     a_p = final[..., 3].cpu().numpy()
     a_0 = plain[..., 3].cpu().numpy()
     assert np.mean(np.abs(a_p - 0.5)) > np.mean(np.abs(a_0 - 0.5))
+
+
+# --------------------------------------------------------------------------------- BF16 refine
+def bf16_ulps(a, b):
+    """Distance in BF16 steps between arrays of BF16 values in [0, 1] (non-negative, so the
+    bit patterns order like the values)."""
+    ua = (np.asarray(a, np.float32).view(np.uint32) >> 16).astype(np.int64)
+    ub = (np.asarray(b, np.float32).view(np.uint32) >> 16).astype(np.int64)
+    return np.abs(ua - ub)
+
+
+def test_refine_bf16_tiny_scene_teacher_forced():
+    """BF16 storage, each iteration of the tiny workload teacher-forced by the oracle's
+    BF16 trajectory (O.refine's steps with bf16=True): selection bit-exact, loss within
+    1e-5 relative, the stored update equal to the oracle's BF16 rounding except where the
+    FP32 gradient's last bits decide a rounding (at most one BF16 step, rarely), and the
+    BF16 upsampling between levels likewise."""
+    sc, init, targets = scene_inputs("c1")
+    plan = hsgd.RefinePlan(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths, sc.W, sc.H,
+                           sc.iters, sc.k, dtype=torch.bfloat16)
+    pyr = O.target_pyramid(targets, sc.levels)
+    M = O.bf16_round(init)
+    flips = total = 0
+    for l, (w, h) in enumerate(plan.shapes):
+        if l > 0:
+            up = hsgd.hsgd_upsample2x(to_dev(M, torch.bfloat16)).float().cpu().numpy()
+            M = O.upsample2x(M, bf16=True)
+            d = bf16_ulps(up, M)
+            assert d.max() <= 1 and np.mean(d > 0) <= 1e-3
+        Gl = oracle_maps(O, dict(K_ref=sc.K_ref(), K=sc.K_views(), R=sc.R_views(), t=sc.t_views(),
+                                 depths=sc.depths, W=sc.W, H=sc.H), w, h)
+        tl = to_dev(pyr[l])
+        for _ in range(sc.iters[l]):
+            S = O.select_active(M[..., 3], sc.k)
+            L_ref, g_ref = O.loss_and_grad(M, Gl, f32(pyr[l]))
+            nxt = O.apply_update(M, g_ref, S, 1.0, 1.0, bf16=True)
+            state = to_dev(M, torch.bfloat16)
+            mask = hsgd.hsgd_select_active(state, sc.k, with_ids=False)
+            assert np.array_equal(mask_bits(mask.cpu().numpy(), sc.D), S)
+            _, loss = hsgd.hsgd_grad_step(state, plan.warps[l], sc.N, images=tl, mask=mask, kcap=sc.k,
+                                          lr_rgb=1.0, lr_alpha=1.0, want_loss=True)
+            assert abs(loss.item() - L_ref) <= 1e-5 * L_ref
+            d = bf16_ulps(state.float().cpu().numpy(), nxt)
+            assert d.max() <= 1
+            flips += int(np.count_nonzero(d))
+            total += d.size
+            M = nxt
+    print(f"BF16 teacher-forced: {flips} of {total} stored values one BF16 step off", flush=True)
+    assert flips <= 1e-3 * total
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_refine_bf16_end_to_end_matches_oracle(name):
+    """hsgd_refine in BF16 storage against O.refine(bf16=True) from the same BF16 initial
+    MPI: per-iteration losses within 1e-4 relative; the final MPIs' PSNR, both rendered by
+    the oracle, within 0.01 dB (the BF16 bar is 0.05 dB); the final MPI equal in nearly
+    every value, at most one BF16 step apart where FP32 rounding decides a stored value,
+    and further apart only on the few voxels whose selection flips where one of those steps
+    moved a near tie (counted and bounded)."""
+    sc, init, targets = scene_inputs(name)
+    M0 = O.bf16_round(init)
+    M_ref, log = O.refine(M0, targets, sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths,
+                          sc.iters, sc.k, 1.0, 1.0, bf16=True)
+    final, losses = hsgd.hsgd_refine(to_dev(M0, torch.bfloat16), to_dev(targets), sc.K_ref(), sc.K_views(),
+                                     sc.R_views(), sc.t_views(), sc.depths, sc.iters, sc.k)
+    torch.cuda.synchronize()
+    assert final.dtype == torch.bfloat16
+    Mf = final.float().cpu().numpy().astype(np.float64)
+    d = bf16_ulps(Mf, M_ref)
+    G = O.view_to_ref_maps(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths)
+    p_ref = O.psnr(O.render(M_ref, G), targets)
+    p_gpu = O.psnr(O.render(Mf, G), targets)
+    ref_losses = np.array([e["loss"] for e in log])
+    got = losses.cpu().numpy()
+    print(f"{name} BF16: losses {got} vs {ref_losses}; PSNR {p_gpu:.4f} vs {p_ref:.4f} dB; "
+          f"{int(np.count_nonzero(d))} values differ ({int(np.sum(d == 1))} by one step, "
+          f"{int(np.sum(d > 1))} by more, max {int(d.max())}) of {d.size}", flush=True)
+    np.testing.assert_allclose(got, ref_losses, rtol=1e-4)
+    assert abs(p_gpu - p_ref) <= 0.01
+    assert np.mean(d > 0) <= 1e-2
+    assert np.mean(d > 1) <= 1e-3

@@ -185,3 +185,70 @@ def test_sparsity_prior_request_equals_refine(mix):
     ref, _ = hsgd.hsgd_refine(si.inits[1], si.targets, sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(),
                               sc.depths, sc.iters, sc.k, lambda_s=lam)
     assert torch.equal(st.result, ref)
+
+
+def test_steps_on_alternating_streams_equal_refine(mix):
+    """Steps enqueued on two different streams in turn run in order (each waits for the
+    step before it): the request equals hsgd_refine alone, bitwise."""
+    si = mix[2]
+    sc = si.sc
+    st = serving.new_stream(0, si)
+    st.levels[0].copy_(si.inits[1])
+    torch.cuda.synchronize()
+    b = hsgd.Batch(1, sc.D, sc.N, sc.H, sc.W, sc.k)
+    assert b.admit(st) is not None
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    i = 0
+    while b.step(stream=streams[i % 2])[0]:
+        i += 1
+    torch.cuda.synchronize()
+    assert i == sum(sc.iters)
+    ref, ref_loss = alone(si, 1, torch.bfloat16)
+    assert torch.equal(st.result, ref)
+    assert torch.equal(st.loss_log[:sum(sc.iters)], ref_loss)
+
+
+def test_served_requests_match_oracle_bf16_refine():
+    """Two requests of different frame sizes and plane counts (256x192x16, k 2 and
+    512x384x32, k 4) served together in one batch, each against the oracle's BF16 refine
+    (O.refine with bf16=True) of the same initial MPI and oracle-rendered targets:
+    per-iteration losses within 1e-4 relative, final-MPI PSNR (both rendered by the oracle)
+    within 0.01 dB, and the final MPI equal up to rare BF16 rounding steps."""
+    from oracle import hsgd_oracle as O
+    from paper_2307_03017_amd import scenes
+    from tests.test_gpu_parity import bf16_ulps
+
+    cases = []
+    for i, (cfg, seed, N) in enumerate((("s256", 100, 3), ("s512", 103, 5))):
+        sc = scenes.make_scene(cfg, seed=seed, N=N)
+        G = O.view_to_ref_maps(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths)
+        targets = np.asarray(O.render(sc.gt_mpi(), G), np.float32).astype(np.float64)
+        w0, h0 = sc.shapes()[0]
+        M0 = O.bf16_round(sc.noisy_mpi(w0, h0, seed=1000 * seed + 7))
+        st = hsgd.ServingStream(i, sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths, sc.W, sc.H,
+                                sc.iters, sc.k, dtype=torch.bfloat16)
+        st.images[-1].copy_(torch.from_numpy(targets.astype(np.float32)).to(DEV))
+        st.levels[0].copy_(torch.from_numpy(M0.astype(np.float32)).to(DEV).to(torch.bfloat16))
+        cases.append((sc, G, targets, M0, st))
+    torch.cuda.synchronize()
+    b = hsgd.Batch(2, 32, 5, 384, 512, 4)
+    for *_, st in cases:
+        assert b.admit(st) is not None
+    while b.step()[0]:
+        pass
+    torch.cuda.synchronize()
+    for sc, G, targets, M0, st in cases:
+        M_ref, log = O.refine(M0, targets, sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths,
+                              sc.iters, sc.k, 1.0, 1.0, bf16=True)
+        Mf = st.result.float().cpu().numpy().astype(np.float64)
+        got = st.loss_log[:sum(sc.iters)].cpu().numpy()
+        ref = np.array([e["loss"] for e in log])
+        d = bf16_ulps(Mf, M_ref)
+        p_ref = O.psnr(O.render(M_ref, G), targets)
+        p_got = O.psnr(O.render(Mf, G), targets)
+        print(f"served {sc.W}x{sc.H}x{sc.D}: losses {got} vs {ref}; PSNR {p_got:.4f} vs {p_ref:.4f} dB; "
+              f"{int(np.count_nonzero(d))} values differ, {int(np.sum(d > 1))} by more than one step",
+              flush=True)
+        np.testing.assert_allclose(got, ref, rtol=1e-4)
+        assert abs(p_got - p_ref) <= 0.01
+        assert np.mean(d > 0) <= 1e-2 and np.mean(d > 1) <= 1e-3

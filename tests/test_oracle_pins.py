@@ -577,3 +577,46 @@ def test_refine_from_ground_truth_stays_put():
     M, log = O.refine(gt0, t0, Kr0, K0, sc.R_views(), sc.t_views(), sc.depths, (2,), sc.k, 1.0, 1.0)
     assert log[0]["loss"] == 0.0
     np.testing.assert_array_equal(M, gt0)
+
+
+# ------------------------------------------------------------------ PSNR (Sec. 5.1 metric, peak 1)
+def test_psnr_closed_forms():
+    """PSNR = 10 log10(1 / MSE) with peak value 1, the MSE taken over every view, pixel and
+    channel: an error of +-0.1 everywhere is 20 dB, +-0.01 is 40 dB; identical images are
+    infinite; one channel of one pixel off by sqrt(0.3) among 300 values (MSE 1e-3) is
+    30 dB (the mean runs over channels too); doubling the error costs 20 log10(2) dB."""
+    rng = RNG(90)
+    C = rng.uniform(0.2, 0.8, size=(2, 12, 10, 3))
+    sign = np.where(rng.uniform(size=C.shape) < 0.5, -1.0, 1.0)
+    assert abs(O.psnr(C + 0.1 * sign, C) - 20.0) <= 1e-9
+    assert abs(O.psnr(C + 0.01 * sign, C) - 40.0) <= 1e-9
+    assert O.psnr(C, C) == float("inf")
+    one = np.zeros((1, 10, 10, 3))
+    bad = one.copy()
+    bad[0, 3, 7, 1] = np.sqrt(0.3)
+    assert abs(O.psnr(bad, one) - 30.0) <= 1e-9
+    e = 0.05 * sign
+    assert abs(O.psnr(C + e, C) - O.psnr(C + 2 * e, C) - 20 * np.log10(2.0)) <= 1e-9
+
+
+def test_refine_logs_the_psnr_of_the_state_it_steps_from():
+    """The refine's logged PSNR at an iteration is the PSNR of the views rendered from the
+    MPI that iteration starts from, against that level's targets: at the first iteration
+    (the initial MPI at the coarsest level) and at the first iteration of the next level
+    (the upsampled result of the coarse iterations, which a refine with no iterations at the
+    finer level returns)."""
+    sc = scenes.make_scene("c1")
+    G = O.view_to_ref_maps(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths)
+    targets = O.render(sc.gt_mpi(), G)
+    args = (sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths)
+    M0 = sc.initial_mpi()
+    _, log = O.refine(M0, targets, *args, (2, 1), sc.k, 1.0, 1.0)
+    M1, _ = O.refine(M0, targets, *args, (2, 0), sc.k, 1.0, 1.0)
+    pyr = O.target_pyramid(targets, 2)
+    for level, state, entry in ((0, M0, log[0]), (1, M1, log[2])):
+        h, w = pyr[level].shape[1:3]
+        Kr = O.level_intrinsics(sc.K_ref(), sc.W, sc.H, w, h)
+        K = np.stack([O.level_intrinsics(k, sc.W, sc.H, w, h) for k in sc.K_views()])
+        Gl = O.view_to_ref_maps(Kr, K, sc.R_views(), sc.t_views(), sc.depths)
+        assert entry["level"] == level
+        assert abs(entry["psnr"] - O.psnr(O.render(state, Gl), pyr[level])) <= 1e-9
