@@ -650,8 +650,9 @@ __device__ __forceinline__ void grad_shift_tile(
     // Transmittance in front of the first kTL planes: these live longest (from the start of
     // the front-to-back scan to the end of the back-to-front one), so at 6 waves per SIMD
     // they go to LDS instead of registers, which would otherwise spill to scratch memory
-    // (whose reloads wait for every load in flight, the look-ahead included).
-    constexpr int kTL = MAXD <= 32 ? 4 : 0;
+    // (whose reloads wait for every load in flight, the look-ahead included). Six planes
+    // keep 32 planes within 80 registers; with 49.5 KB of LDS three workgroups fit a CU.
+    constexpr int kTL = MAXD <= 32 ? 6 : 0;
     __shared__ float s_T[kTL > 0 ? kTL : 1][kSX * kSY];
     const int view = tile % N;
     const int t2 = tile / N;
@@ -665,27 +666,38 @@ __device__ __forceinline__ void grad_shift_tile(
     const int HW = H * W;
     const uint64_t full = plane_bits(D);
 
-    // Plane tables. Lane z < D holds plane z's integer shift (read per plane with
-    // v_readlane: it feeds scalar address arithmetic). The bilinear weights of each plane
-    // for this wave's row (lerp_taps' four; a tap row outside the plane weighted 0) and the
-    // shift's fraction go to LDS, read per plane as broadcasts. Planes z >= D get zeros.
-    int lx = 0, ly = 0;
+    // Plane tables, one entry per lane z < MAXD (read per plane with v_readlane, feeding
+    // scalar address arithmetic):
+    //   lrow  byte offset, within plane z, of this wave's upper tap row y + iy clamped into
+    //         the plane, | 1 if that row lies in the plane, | 2 if the row below it does,
+    //         | 4 if the row below is the plane's first row (the upper one lies above it);
+    //   lcol  the integer column shift times the voxel size (ix * s).
+    // A wave's tap columns are then x + ix for its lanes' x.
+    // The bilinear weights of each plane for this wave's row (lerp_taps' four; a tap row
+    // outside the plane weighted 0) and the shift's fraction go to LDS, read per plane as
+    // broadcasts. Planes z >= D repeat plane D - 1 with zero weights.
+    constexpr int S = Vox<DT>::kBytes;
+    const int rowbytes = W * S;
+    const int dlast = __builtin_amdgcn_readfirstlane(D - 1);    // last plane, wave-uniform
+    int lrow = 0, lcol = 0;
     if (lane < MAXD) {
         float4 wt = make_float4(0.f, 0.f, 0.f, 0.f);
         float2 fr = make_float2(0.f, 0.f);
+        const hsgd_warp& w = warps[(size_t)view * D + min(lane, dlast)];
+        const int Y0 = y + w.iy;
+        const bool in0 = (unsigned)Y0 < (unsigned)H, in1 = (unsigned)(Y0 + 1) < (unsigned)H;
+        lrow = min(max(Y0, 0), H - 1) * rowbytes | (in0 ? 1 : 0) | (in1 ? 2 : 0) | (Y0 == -1 ? 4 : 0);
+        // (a shift beyond the frame and its halo only ever reads padding; clamping it there
+        // keeps every lane's byte offset from wrapping into the row)
+        lcol = min(max(w.ix, -(W + 64)), W + 64) * S;
         if (lane < D) {
-            const hsgd_warp& w = warps[(size_t)view * D + lane];
-            lx = w.ix;
-            ly = w.iy;
             fr = make_float2(w.fx, w.fy);
-            const int Y0 = y + ly;
-            const float gy = (unsigned)Y0 < (unsigned)H ? 1.0f - fr.y : 0.0f;
-            const float hy = (unsigned)(Y0 + 1) < (unsigned)H ? fr.y : 0.0f;
-            wt = make_float4(gy, hy, 1.0f - fr.x, fr.x);
+            wt = make_float4(in0 ? 1.0f - fr.y : 0.0f, in1 ? fr.y : 0.0f, 1.0f - fr.x, fr.x);
         }
         s_w[wv][lane] = wt;
         if (wv == 0) s_f[lane] = fr;
     }
+    const unsigned xs = (unsigned)x * (unsigned)S;                // wraps when x < 0: outside
     __syncthreads();
 
     // Both scans run over MAXD planes; planes z >= D sample plane D-1 with zero weights (a
@@ -696,36 +708,36 @@ __device__ __forceinline__ void grad_shift_tile(
     // for several workgroups per CU, which hides the per-plane barrier.
     struct Taps2 {
         float4 t00, t01;   // taps of rows y0 and y0 + 1 (right-hand taps come from lane + 1)
-        int ix, iy;        // the plane's integer shift (wave-uniform), carried with its taps
+        unsigned row;      // in-plane byte offset of the upper tap row, with lrow's flags
+        unsigned col;      // the column shift in bytes (ix * s), wave-uniform
+        // byte offset of this lane's tap column in a row: (x + ix) * s
+        __device__ unsigned off(unsigned xs_) const { return xs_ + col; }
     };
-    // zstride: the plane stride HW, passed laundered to the second scan so that the
-    // compiler cannot prove its loads equal the first scan's and keep those alive instead
+    // zstride: the plane stride in voxels (H W), passed laundered to the second scan so that
+    // the compiler cannot prove its loads equal the first scan's and keep those alive instead.
     // Taps come through buffer resources over the two tap rows: a column outside the
     // plane, or a whole row outside it, reads as 0 -- the zero padding -- so neither the
     // addresses nor the weights need per-lane range checks.
     auto fetch = [&](int z, int zstride) {
         Taps2 f;
-        const int ix = rl(lx, z), iy = rl(ly, z);
-        f.ix = ix;
-        f.iy = iy;
-        const int zb = min(z, D - 1) * zstride;
-        const int Y0 = y + iy;
-        const int rb = W * Vox<DT>::kBytes;
-        const unsigned off = (unsigned)(x + ix) * (unsigned)Vox<DT>::kBytes;   // wraps when < 0: outside
-        const bool r0 = (unsigned)Y0 < (unsigned)H, r1 = (unsigned)(Y0 + 1) < (unsigned)H;
-        f.t00 = Vox<DT>::load_buf(row_rsrc(Vox<DT>::row_ptr(mpi, zb + (r0 ? Y0 : 0) * W), r0 ? rb : 0), off);
-        f.t01 = Vox<DT>::load_buf(row_rsrc(Vox<DT>::row_ptr(mpi, zb + (r1 ? Y0 + 1 : 0) * W), r1 ? rb : 0), off);
+        f.row = (unsigned)rl(lrow, z);
+        f.col = (unsigned)rl(lcol, z);
+        const char* plane = reinterpret_cast<const char*>(mpi) + (size_t)((unsigned)min(z, dlast) * (unsigned)zstride) * S;
+        const char* row0 = plane + (f.row & ~7u);
+        const char* row1 = row0 + ((f.row & 4u) ? 0u : (unsigned)rowbytes);
+        const unsigned off = f.off(xs);
+        f.t00 = Vox<DT>::load_buf(row_rsrc(row0, (f.row & 1u) ? rowbytes : 0), off);
+        f.t01 = Vox<DT>::load_buf(row_rsrc(row1, (f.row & 2u) ? rowbytes : 0), off);
         return f;
     };
-    // the owned cell's mask word (the tap column is the cell's column), through a buffer
-    // resource over the cell's mask row: a cell outside the plane reads 0, i.e. unselected
+    // the owned cell's mask word (the cell is the upper tap row's voxel of this lane's
+    // column), through a buffer resource over the cell's mask row: a cell outside the
+    // plane reads 0, i.e. unselected
     auto fetch_mask = [&](const Taps2& f) -> uint64_t {
         if (!MASKED) return full;
-        const int Y = y + f.iy;
-        const bool rv = (unsigned)Y < (unsigned)H;
-        const char* row = reinterpret_cast<const char*>(mask) + (size_t)(unsigned)((rv ? Y : 0) * W) * 8;
-        const auto v = __builtin_amdgcn_raw_buffer_load_b64(row_rsrc(row, rv ? W * 8 : 0),
-                                                            (unsigned)(x + f.ix) * 8u, 0, 0);
+        const char* row = reinterpret_cast<const char*>(mask) + (f.row & ~7u) / (unsigned)(S / 8);
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(row_rsrc(row, (f.row & 1u) ? W * 8 : 0),
+                                                            f.off(xs) / (unsigned)(S / 8), 0, 0);
         return ((uint64_t)v[1] << 32) | v[0];
     };
     auto sample = [&](int z, const Taps2& f) {
@@ -778,8 +790,7 @@ __device__ __forceinline__ void grad_shift_tile(
             c2 += wgt * s.z;
             T *= 1.0f - s.w;
             // (a cell outside the plane has a zero mask word; without a mask, check the range)
-            const bool cell = owner && z < D &&
-                              (MASKED || ((unsigned)(y + cur.iy) < (unsigned)H && (unsigned)(x + cur.ix) < (unsigned)W));
+            const bool cell = owner && z < D && (MASKED || ((cur.row & 1u) && cur.off(xs) < (unsigned)rowbytes));
             // branch-free: rank + 1 of the owned cell's plane z if selected, else 0
             const uint32_t sel = cell ? (uint32_t)((m >> z) & 1) : 0u;
             const uint32_t rank = (uint32_t)__popcll(m & ((1ull << z) - 1));
@@ -813,7 +824,8 @@ __device__ __forceinline__ void grad_shift_tile(
 
     float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, sq = 0.0f;
     if (ray) {
-        const size_t pix = ((size_t)view * H + y) * W + x;
+        // (x again from the lane's tap offset, so that x itself need not stay live)
+        const size_t pix = ((size_t)view * H + y) * W + (int)xs / S;
         if (images) {
             const float d0 = c0 - images[3 * pix + 0];
             const float d1 = c1 - images[3 * pix + 1];
@@ -834,7 +846,7 @@ __device__ __forceinline__ void grad_shift_tile(
     // launder what the second scan derives its taps from, so that nothing computed per
     // plane in the first scan is kept alive for it
     int HW2 = HW;
-    asm volatile("" : "+s"(HW2), "+v"(lx), "+v"(ly));
+    asm volatile("" : "+s"(HW2), "+v"(lrow), "+v"(lcol));
     uint32_t rcode = 0;
     {
         Taps2 q[kAhead];
@@ -853,6 +865,9 @@ __device__ __forceinline__ void grad_shift_tile(
             if ((z & 3) == 3 || z == MAXD - 1) rcode = s_code[z >> 2][tid];
             const float4 s = sample(z, cur);
             float4* buf = s_h[z & 1];
+            // the colour of plane z against the composite behind it: the alpha adjoint's
+            // factor and the step of the behind composite, B <- B + a (c - B)
+            const float d0 = s.x - b0, d1 = s.y - b1, d2 = s.z - b2;
             if ((need_bits >> z) & 1) {
                 const float Tz = z < kTL ? s_T[z < kTL ? z : 0][tid] : Ts[z];
                 const float ca = s.w * Tz;
@@ -860,7 +875,7 @@ __device__ __forceinline__ void grad_shift_tile(
                 a.x = g0 * ca;
                 a.y = g1 * ca;
                 a.z = g2 * ca;
-                a.w = Tz * (g0 * (s.x - b0) + g1 * (s.y - b1) + g2 * (s.z - b2));
+                a.w = Tz * (g0 * d0 + g1 * d1 + g2 * d2);
                 // horizontal half of the transposed bilinear: this ray (1 - fx) and the
                 // ray to the left (fx) both touch the owned cell's row
                 const float gx = 1.0f - fx;
@@ -871,10 +886,9 @@ __device__ __forceinline__ void grad_shift_tile(
                 h.w = __builtin_fmaf(a.w, gx, lane_from_prev(a.w) * fx);
                 buf[tid] = h;
             }
-            const float oa = 1.0f - s.w;
-            b0 = s.w * s.x + oa * b0;
-            b1 = s.w * s.y + oa * b1;
-            b2 = s.w * s.z + oa * b2;
+            b0 = __builtin_fmaf(s.w, d0, b0);
+            b1 = __builtin_fmaf(s.w, d1, b1);
+            b2 = __builtin_fmaf(s.w, d2, b2);
             __syncthreads();
             if ((own_bits >> z) & 1) {
                 const int rc = (int)((rcode >> ((z & 3) * 8)) & 0xffu);
@@ -889,8 +903,11 @@ __device__ __forceinline__ void grad_shift_tile(
                     c.y = h.y * gy + hu.y * fy;
                     c.z = h.z * gy + hu.z * fy;
                     c.w = h.w * gy + hu.w * fy;
-                    const unsigned idx = (unsigned)((rc - 1) * HW + (y + cur.iy) * W + (x + cur.ix));
-                    *reinterpret_cast<float4*>(reinterpret_cast<char*>(vslots) + (idx << 4)) = c;
+                    // slot (rank, cell): the cell's byte offset in an FP32 RGBA plane is its
+                    // tap offsets scaled from the storage's voxel size to 16 bytes
+                    const unsigned cell16 = ((cur.row & ~7u) + cur.off(xs)) * (unsigned)(16 / S);
+                    const unsigned idx = (unsigned)(rc - 1) * (unsigned)HW * 16u + cell16;
+                    *reinterpret_cast<float4*>(reinterpret_cast<char*>(vslots) + idx) = c;
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
