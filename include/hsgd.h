@@ -290,6 +290,26 @@ hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
                         size_t ws_bytes, hipStream_t stream);
 
 /*
+ * hsgd_refine_noalloc -- hsgd_refine for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid allocation): the same
+ * arguments and results without ws / ws_bytes. Its workspace is a static device array of
+ * HSGD_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on until the
+ * process ends; the call itself allocates and frees nothing (while hsgd_profile_* timing
+ * is off). The refine's workspace (hsgd_workspace_bytes(HSGD_OP_REFINE, ...)) must fit in
+ * it: 512x384 with 32 planes, 4 views and k = 4 needs 52.3 MiB and fits; larger calls
+ * fail with HSGD_E_WORKSPACE and enqueue nothing. The array is looked up once per device
+ * (with that device current) on the first call whose stream is on it. Every call on one
+ * GPU uses that GPU's one array: calls that overlap on a GPU (on different streams, or
+ * from several threads) race and corrupt each other's results; calls ordered on one
+ * stream are safe. Nothing in the array needs to start at zero (the kernels write every
+ * workspace value they read first, or clear it with a fill kernel).
+ */
+#define HSGD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+hsgd_status hsgd_refine_noalloc(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
+                                const int32_t* iters, hsgd_select_params sel, float lr_rgb,
+                                float lr_alpha, float lambda_s, float* loss_log, hipStream_t stream);
+
+/*
  * hsgd_convert -- storage conversion of n floats: FP32 -> BF16 (round to nearest even),
  * BF16 -> FP32 (exact) or a plain copy for equal types. src, dst device.
  */

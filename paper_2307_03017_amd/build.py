@@ -38,6 +38,7 @@ HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__"]
 SOURCES = [
     ("hsgd_kernels.hip", "device"),
     ("hsgd_psv.hip", "device"),
+    ("hsgd_noalloc.hip", "device"),
     ("hsgd_api.cpp", "host"),
     ("hsgd_host.cpp", "host"),
     ("hsgd_profile.cpp", "host"),

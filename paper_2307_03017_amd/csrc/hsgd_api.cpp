@@ -8,10 +8,12 @@
 
 using namespace hsgd;
 
-static hsgd_status hip_status(int err, const char* what) {
+namespace hsgd {
+hsgd_status hip_status(int err, const char* what) {
     if (err == hipSuccess) return HSGD_OK;
     return fail(HSGD_E_HIP, "%s: %s", what, hipGetErrorString((hipError_t)err));
 }
+}  // namespace hsgd
 
 extern "C" {
 
@@ -149,6 +151,21 @@ hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
                         size_t ws_bytes, hipStream_t stream) {
     clear_error();
     const char* fn = "hsgd_refine";
+    size_t need = 0;
+    hsgd_status st = refine_check(fn, levels, views, L, iters, sel, lr_rgb, lr_alpha, lambda_s, &need);
+    if (st) return st;
+    st = check_ws(ws, ws_bytes, need);
+    if (st) return st;
+    return refine_run(fn, levels, views, L, iters, sel, lr_rgb, lr_alpha, lambda_s, loss_log, ws, stream);
+}
+
+}  // extern "C"
+
+namespace hsgd {
+
+hsgd_status refine_check(const char* fn, const hsgd_mpi* levels, const hsgd_views* views, int32_t L,
+                         const int32_t* iters, hsgd_select_params sel, float lr_rgb, float lr_alpha,
+                         float lambda_s, size_t* ws_need) {
     if (!levels || !views || !iters) return fail(HSGD_E_ARG, "%s: NULL pointer", fn);
     if (L < 1 || L > 16) return fail(HSGD_E_ARG, "%s: L=%d outside [1, 16]", fn, L);
     hsgd_status st;
@@ -177,10 +194,16 @@ hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
         return fail(HSGD_E_ARG, "%s: unknown selection rule %d", fn, sel.rule);
     if (!std::isfinite(lr_rgb) || !std::isfinite(lr_alpha) || !std::isfinite(lambda_s))
         return fail(HSGD_E_ARG, "%s: learning rates and lambda_s must be finite", fn);
+    *ws_need = refine_ws(top.D, top.H, top.W, views[0].N, sel.k, L).bytes;
+    return HSGD_OK;
+}
+
+hsgd_status refine_run(const char* fn, hsgd_mpi* levels, const hsgd_views* views, int32_t L, const int32_t* iters,
+                       hsgd_select_params sel, float lr_rgb, float lr_alpha, float lambda_s, float* loss_log,
+                       void* ws, hipStream_t stream) {
+    const hsgd_mpi& top = levels[L - 1];
     const int N = views[0].N;
     const RefineWs R = refine_ws(top.D, top.H, top.W, N, sel.k, L);
-    st = check_ws(ws, ws_bytes, R.bytes);
-    if (st) return st;
 
     // target pyramid: coarser images that were not given are box means of the finer ones
     const float* img[16];
@@ -223,4 +246,4 @@ hsgd_status hsgd_refine(hsgd_mpi* levels, const hsgd_views* views, int32_t L,
     return HSGD_OK;
 }
 
-}  // extern "C"
+}  // namespace hsgd

@@ -86,6 +86,18 @@ RefineWs refine_ws(int D, int H, int W, int N, int k, int L);
 
 size_t dtype_bytes(int dtype);  // bytes per RGBA voxel, 0 for unknown
 
+// ---- refine (hsgd_api.cpp), shared by hsgd_refine and hsgd_refine_noalloc ----
+// HSGD_E_HIP with the HIP error text, or HSGD_OK for hipSuccess.
+hsgd_status hip_status(int err, const char* what);
+// Validates a refine call and reports the workspace bytes it needs; enqueues nothing.
+hsgd_status refine_check(const char* fn, const hsgd_mpi* levels, const hsgd_views* views, int32_t L,
+                         const int32_t* iters, hsgd_select_params sel, float lr_rgb, float lr_alpha,
+                         float lambda_s, size_t* ws_need);
+// Enqueues a validated refine with its workspace at ws (refine_ws bytes).
+hsgd_status refine_run(const char* fn, hsgd_mpi* levels, const hsgd_views* views, int32_t L, const int32_t* iters,
+                       hsgd_select_params sel, float lr_rgb, float lr_alpha, float lambda_s, float* loss_log,
+                       void* ws, hipStream_t stream);
+
 // ---- kernel timing (hsgd_profile.cpp) ----
 constexpr int kNumKinds = HSGD_K_COUNT;
 const char* kind_name(int kind);

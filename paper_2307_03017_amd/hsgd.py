@@ -104,6 +104,8 @@ _SIGS = {
     "hsgd_plane_sweep": (_I, [ctypes.POINTER(Views), _I, _I, _I, _P, _P]),
     "hsgd_refine": (_I, [ctypes.POINTER(Mpi), ctypes.POINTER(Views), _I, _P, SelectParams, _F, _F, _F,
                          _P, _P, ctypes.c_size_t, _P]),
+    "hsgd_refine_noalloc": (_I, [ctypes.POINTER(Mpi), ctypes.POINTER(Views), _I, _P, SelectParams, _F, _F, _F,
+                                 _P, _P]),
     "hsgd_convert": (_I, [_P, _I, _P, _I, ctypes.c_size_t, _P]),
     "hsgd_profile_begin": (_I, [ctypes.c_uint32]),
     "hsgd_profile_end": (_I, []),
@@ -121,7 +123,9 @@ _SIGS = {
     "hsgd_batch_budget_used": (ctypes.c_int64, [_P]),
 }
 
-HSGD_E_CAPACITY, HSGD_E_BUDGET = -4, -7
+HSGD_E_CAPACITY, HSGD_E_WORKSPACE, HSGD_E_BUDGET = -4, -5, -7
+# bytes of the static device scratch that hsgd_refine_noalloc uses as its workspace
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 K_SELECT, K_SCAN, K_COMPACT, K_RENDER, K_GRAD, K_UPDATE, K_FILL, K_REDUCE, K_UPSAMPLE, \
     K_DOWNSAMPLE, K_CONVERT, K_PSV = range(12)
@@ -525,12 +529,18 @@ class RefinePlan:
             vs.append(views_desc(self.warps[l], self.N, h, w, img, D=self.D))
         return mpis, (Views * self.L)(*vs)
 
-    def run(self, images: torch.Tensor, descriptors=None, stream=None):
-        """Refine levels[0] (the initial MPI, already written by the caller) up to levels[-1]."""
+    def run(self, images: torch.Tensor, descriptors=None, stream=None, noalloc: bool = False):
+        """Refine levels[0] (the initial MPI, already written by the caller) up to levels[-1].
+        noalloc: through hsgd_refine_noalloc, whose workspace is the library's static device
+        scratch (the plan's own workspace is then unused)."""
         mpis, vs = descriptors or self.descriptors(images)
-        _check(lib().hsgd_refine(mpis, vs, self.L, self._iters, self.sel,
-                                 self.lr_rgb, self.lr_alpha, self.lambda_s, _ptr(self.loss_log), _ptr(self.ws),
-                                 self.ws.numel(), _stream(stream)))
+        if noalloc:
+            _check(lib().hsgd_refine_noalloc(mpis, vs, self.L, self._iters, self.sel, self.lr_rgb, self.lr_alpha,
+                                             self.lambda_s, _ptr(self.loss_log), _stream(stream)))
+        else:
+            _check(lib().hsgd_refine(mpis, vs, self.L, self._iters, self.sel,
+                                     self.lr_rgb, self.lr_alpha, self.lambda_s, _ptr(self.loss_log), _ptr(self.ws),
+                                     self.ws.numel(), _stream(stream)))
         return self.levels[-1]
 
 

@@ -303,3 +303,27 @@ def test_binding_rejects_warp_tables_and_masks_that_do_not_fit():
         hsgd._check_mask(torch.zeros((16, 12), dtype=torch.int64).t(), m, "cpu")
     hsgd._check_mask(torch.zeros((12, 16), dtype=torch.int64), m, "cpu")
 
+
+def test_refine_noalloc_validates_and_rejects_frames_beyond_its_scratch():
+    """hsgd_refine_noalloc validates like hsgd_refine and refuses a refine whose workspace
+    exceeds the static scratch with HSGD_E_WORKSPACE, before touching any device."""
+    L = hsgd.lib()
+    sp = hsgd.SelectParams
+    it = (ctypes.c_int32 * 3)(1, 1, 1)
+
+    def call(W, H, D, N, k):
+        lv = (hsgd.Mpi * 3)(*[_mpi(D=D, H=H >> (2 - l), W=W >> (2 - l), ptr=0x1000 * (l + 1)) for l in range(3)])
+        vs = (hsgd.Views * 3)(*[_views(N=N, H=H >> (2 - l), W=W >> (2 - l), images=None if l < 2 else FAKE)
+                                for l in range(3)])
+        return L.hsgd_refine_noalloc(lv, vs, 3, it, sp(k, -1), 1.0, 1.0, 0.0, None, None)
+
+    need = L.hsgd_workspace_bytes(hsgd.OP_REFINE, 32, 756, 1008, 5, 4, 3)
+    assert need > hsgd.NOALLOC_SCRATCH_BYTES
+    assert call(1008, 756, 32, 5, 4) == hsgd.HSGD_E_WORKSPACE
+    msg = L.hsgd_last_error().decode()
+    assert "hsgd_refine_noalloc" in msg and str(need) in msg and str(hsgd.NOALLOC_SCRATCH_BYTES) in msg
+    # the benchmark frame fits
+    assert L.hsgd_workspace_bytes(hsgd.OP_REFINE, 32, 384, 512, 4, 4, 3) <= hsgd.NOALLOC_SCRATCH_BYTES
+    # the same argument checks as hsgd_refine
+    assert call(512, 384, 32, 4, 33) == -1
+    assert L.hsgd_refine_noalloc(None, None, 3, it, sp(4, -1), 1.0, 1.0, 0.0, None, None) == -1
