@@ -59,22 +59,23 @@ typedef enum {
 
 typedef enum { HSGD_FP32 = 0, HSGD_BF16 = 1 } hsgd_dtype;
 
-/* Per (view, plane) pixel map, 64 bytes. From hsgd_build_warps: view pixel (x, y, 1) ->
+/* Per (view, plane) pixel map, 96 bytes. From hsgd_build_warps: view pixel (x, y, 1) ->
  * reference pixel on that plane, the inverse of the plane homography H_i^{-1}(d_z) of
  * Eq. (homo) (the direction rendering gathers in). From hsgd_build_psv_warps: reference
  * pixel -> view pixel, H_i^{-1}(d_z) itself (the plane-sweep direction).
- *  G        row-major 3x3 (FP32 copy of the FP64 map), divided by |G[8]|: positions are
- *           unchanged and the sign of the homogeneous coordinate is kept (a point with
- *           q2 <= 0 is behind the camera and samples as transparent / 0);
+ *  G        row-major 3x3 FP64 map, divided by |G[8]|: positions are unchanged and the
+ *           sign of the homogeneous coordinate is kept (a point with q2 <= 0 is behind
+ *           the camera and samples as transparent / 0). The kernels evaluate positions
+ *           from it in FP64 and round only the bilinear fractions to FP32;
  *  is_shift 1 when the map is a pure translation (identity rotation, no z translation,
  *           equal intrinsics). Then the mapped position is (x + ix + fx, y + iy + fy)
  *           exactly: ix, iy integers, fx, fy in [0, 1) rounded once from FP64. */
 typedef struct {
-    float G[9];
+    double G[9];
     int32_t is_shift;
     int32_t ix, iy;
     float fx, fy;
-    int32_t pad[2];
+    int32_t pad;
 } hsgd_warp;
 
 /* An MPI level. rgba: device, [D][H][W][4] of float (HSGD_FP32) or bfloat16 (HSGD_BF16). */

@@ -43,20 +43,27 @@ __device__ __forceinline__ Taps make_taps(const hsgd_warp& wp, int x, int y, int
         fx = wp.fx;
         fy = wp.fy;
     } else {
-        const float xf = (float)x, yf = (float)y;
-        float q0 = wp.G[0] * xf + wp.G[1] * yf + wp.G[2];
-        float q1 = wp.G[3] * xf + wp.G[4] * yf + wp.G[5];
-        float q2 = wp.G[6] * xf + wp.G[7] * yf + wp.G[8];
-        front = q2 > 0.0f;
-        float u = front ? q0 / q2 : -8.0f;
-        float v = front ? q1 / q2 : -8.0f;
-        u = fminf(fmaxf(u, -8.0f), (float)W + 8.0f);   // NaN -> -8 (outside)
-        v = fminf(fmaxf(v, -8.0f), (float)H + 8.0f);
-        float fu = floorf(u), fv = floorf(v);
+        // The position in FP64 from the FP64 map: its error (~1e-12 px) is far below the
+        // FP32 rounding of the fractions, so the taps and weights are those of the exact
+        // position, as for a translation.
+        const double xd = (double)x, yd = (double)y;
+        const double q0 = __builtin_fma(wp.G[0], xd, __builtin_fma(wp.G[1], yd, wp.G[2]));
+        const double q1 = __builtin_fma(wp.G[3], xd, __builtin_fma(wp.G[4], yd, wp.G[5]));
+        const double q2 = __builtin_fma(wp.G[6], xd, __builtin_fma(wp.G[7], yd, wp.G[8]));
+        front = q2 > 0.0;
+        double u = -8.0, v = -8.0;
+        if (front) {
+            const double r = 1.0 / q2;
+            u = q0 * r;
+            v = q1 * r;
+        }
+        u = fmin(fmax(u, -8.0), (double)W + 8.0);   // NaN -> -8 (outside)
+        v = fmin(fmax(v, -8.0), (double)H + 8.0);
+        const double fu = floor(u), fv = floor(v);
         x0 = (int)fu;
         y0 = (int)fv;
-        fx = u - fu;
-        fy = v - fv;
+        fx = (float)(u - fu);
+        fy = (float)(v - fv);
     }
     const bool bx0 = (unsigned)x0 < (unsigned)W, bx1 = (unsigned)(x0 + 1) < (unsigned)W;
     const bool by0 = (unsigned)y0 < (unsigned)H, by1 = (unsigned)(y0 + 1) < (unsigned)H;

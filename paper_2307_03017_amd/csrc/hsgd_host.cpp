@@ -259,7 +259,7 @@ static hsgd_status build_maps(const double* K_ref, const double* K, const double
             for (double& g : G) g *= s;
             hsgd_warp& w = tmp[(size_t)i * D + z];
             memset(&w, 0, sizeof w);
-            for (int j = 0; j < 9; ++j) w.G[j] = (float)G[j];
+            for (int j = 0; j < 9; ++j) w.G[j] = G[j];
             const double eps = 1e-12;
             bool shift = std::fabs(G[0] - 1) <= eps && std::fabs(G[4] - 1) <= eps &&
                          std::fabs(G[1]) <= eps && std::fabs(G[3]) <= eps &&

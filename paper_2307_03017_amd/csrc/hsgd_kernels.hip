@@ -123,9 +123,10 @@ __device__ __forceinline__ float block_sum(float v, float* sh) {
 }
 
 __device__ __forceinline__ void load_warps(hsgd_warp* sw, const hsgd_warp* warps, int view, int D) {
+    constexpr int kWords = (int)(sizeof(hsgd_warp) / sizeof(int));
     const int* src = reinterpret_cast<const int*>(warps + (size_t)view * D);
     int* dst = reinterpret_cast<int*>(sw);
-    for (int i = threadIdx.x; i < D * 16; i += blockDim.x) dst[i] = src[i];
+    for (int i = threadIdx.x; i < D * kWords; i += blockDim.x) dst[i] = src[i];
 }
 
 // ------------------------------------------------------------------------------------

@@ -30,9 +30,9 @@ class HsgdError(RuntimeError):
 
 
 class Warp(ctypes.Structure):
-    _fields_ = [("G", ctypes.c_float * 9), ("is_shift", ctypes.c_int32), ("ix", ctypes.c_int32),
+    _fields_ = [("G", ctypes.c_double * 9), ("is_shift", ctypes.c_int32), ("ix", ctypes.c_int32),
                 ("iy", ctypes.c_int32), ("fx", ctypes.c_float), ("fy", ctypes.c_float),
-                ("pad", ctypes.c_int32 * 2)]
+                ("pad", ctypes.c_int32)]
 
 
 class Mpi(ctypes.Structure):
@@ -63,7 +63,8 @@ def select_params(k: int, tau: float = -1.0, rule="topk") -> SelectParams:
     return SelectParams(int(k), float(tau), _RULES[rule])
 
 
-assert ctypes.sizeof(Warp) == 64
+WARP_BYTES = 96
+assert ctypes.sizeof(Warp) == WARP_BYTES
 
 MAX_BATCH_LEVELS = 4
 
@@ -248,9 +249,9 @@ def views_desc(warps, N: int, H: int, W: int, images: torch.Tensor | None = None
             raise ValueError(f"warp table has {warps.N} views, {N} requested")
         flags = warps.flags
         warps = warps.tensor
-    need = N * (1 if D is None else D) * 64
+    need = N * (1 if D is None else D) * WARP_BYTES
     if warps.numel() * warps.element_size() < need:
-        raise ValueError(f"warp table holds fewer than N x D = {need // 64} records")
+        raise ValueError(f"warp table holds fewer than N x D = {need // WARP_BYTES} records")
     _dev(warps, "warps")
     _dev(images, "images")
     _f32(images, "images")
@@ -274,12 +275,12 @@ def workspace(op: int, D: int, H: int, W: int, N: int, k: int, L: int = 1, devic
 # host calls
 # ---------------------------------------------------------------------------------------
 def hsgd_build_warps(K_ref, K, R, t, depths) -> np.ndarray:
-    """FP64 plane maps for N views x D planes; returns a uint8 array [N][D][64] (hsgd_warp)."""
+    """FP64 plane maps for N views x D planes; returns a uint8 array [N][D][WARP_BYTES] (hsgd_warp)."""
     return _build_maps("hsgd_build_warps", K_ref, K, R, t, depths)
 
 
 def hsgd_build_psv_warps(K_ref, K, R, t, depths) -> np.ndarray:
-    """FP64 plane-sweep maps (reference pixel on plane z -> source view i), [N][D][64]."""
+    """FP64 plane-sweep maps (reference pixel on plane z -> source view i), [N][D][WARP_BYTES]."""
     return _build_maps("hsgd_build_psv_warps", K_ref, K, R, t, depths)
 
 
@@ -295,13 +296,13 @@ def _build_maps(fn, K_ref, K, R, t, depths) -> np.ndarray:
     out = (Warp * (N * D))()
     _check(getattr(lib(), fn)(K_ref.ctypes.data, K.ctypes.data, R.ctypes.data, t.ctypes.data,
                               depths.ctypes.data, N, D, ctypes.addressof(out)))
-    return np.frombuffer(bytes(out), dtype=np.uint8).reshape(N, D, 64).copy()
+    return np.frombuffer(bytes(out), dtype=np.uint8).reshape(N, D, WARP_BYTES).copy()
 
 
 def warp_records(raw: np.ndarray) -> list:
     """Decode hsgd_build_warps output into Warp structures (for inspection and tests)."""
     buf = np.ascontiguousarray(raw, dtype=np.uint8).tobytes()
-    n = len(buf) // 64
+    n = len(buf) // WARP_BYTES
     arr = (Warp * n).from_buffer_copy(buf)
     return list(arr)
 
@@ -433,7 +434,7 @@ def hsgd_plane_sweep(images: torch.Tensor, warps, D: int, L: int = 1, store=None
     if isinstance(warps, WarpTable):
         if (warps.N, warps.D) != (N, D):
             raise ValueError(f"warp table is {warps.N} x {warps.D}, expected {N} x {D}")
-    elif warps.numel() < N * D * 64:
+    elif warps.numel() * warps.element_size() < N * D * WARP_BYTES:
         raise ValueError("warp table holds fewer than N * D records")
     v = views_desc(warps, N, H, W, images, D=D, device=images.device)
     store = [True] * L if store is None else list(store)
