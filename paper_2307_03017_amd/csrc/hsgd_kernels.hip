@@ -52,6 +52,9 @@ struct Vox<HSGD_FP32> {
     }
     static constexpr int kBytes = 16;
     static __device__ __forceinline__ float4 stored(float4 v) { return v; }
+    using Raw = float4;                                     // a voxel as stored
+    static __device__ __forceinline__ Raw load_raw(__amdgpu_buffer_rsrc_t r, unsigned off) { return load_buf(r, off); }
+    static __device__ __forceinline__ float4 decode(const Raw& v) { return v; }
 };
 
 template <>
@@ -84,6 +87,15 @@ struct Vox<HSGD_BF16> {
                            __uint_as_float(v[1] << 16), __uint_as_float(v[1] & 0xffff0000u));
     }
     static constexpr int kBytes = 8;
+    using Raw = uint2;                                      // a voxel as stored
+    static __device__ __forceinline__ Raw load_raw(__amdgpu_buffer_rsrc_t r, unsigned off) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+        return make_uint2(v[0], v[1]);
+    }
+    static __device__ __forceinline__ float4 decode(const Raw& v) {
+        return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u),
+                           __uint_as_float(v.y << 16), __uint_as_float(v.y & 0xffff0000u));
+    }
     // the value a store followed by a load returns (round to nearest even, NaN quieted)
     static __device__ __forceinline__ float4 stored(float4 v) {
         return make_float4(__uint_as_float(f32_to_bf16_bits(v.x) << 16), __uint_as_float(f32_to_bf16_bits(v.y) << 16),
@@ -708,7 +720,7 @@ __device__ __forceinline__ void grad_shift_tile(
     // planes again instead of keeping them in registers: that keeps the kernel small enough
     // for several workgroups per CU, which hides the per-plane barrier.
     struct Taps2 {
-        float4 t00, t01;   // taps of rows y0 and y0 + 1 (right-hand taps come from lane + 1)
+        typename Vox<DT>::Raw t00, t01;   // taps of rows y0 and y0 + 1, as stored (right-hand taps come from lane + 1)
         unsigned row;      // in-plane byte offset of the upper tap row, with lrow's flags
         unsigned col;      // the column shift in bytes (ix * s), wave-uniform
         // byte offset of this lane's tap column in a row: (x + ix) * s
@@ -727,8 +739,8 @@ __device__ __forceinline__ void grad_shift_tile(
         const char* row0 = plane + (f.row & ~7u);
         const char* row1 = row0 + ((f.row & 4u) ? 0u : (unsigned)rowbytes);
         const unsigned off = f.off(xs);
-        f.t00 = Vox<DT>::load_buf(row_rsrc(row0, (f.row & 1u) ? rowbytes : 0), off);
-        f.t01 = Vox<DT>::load_buf(row_rsrc(row1, (f.row & 2u) ? rowbytes : 0), off);
+        f.t00 = Vox<DT>::load_raw(row_rsrc(row0, (f.row & 1u) ? rowbytes : 0), off);
+        f.t01 = Vox<DT>::load_raw(row_rsrc(row1, (f.row & 2u) ? rowbytes : 0), off);
         return f;
     };
     // the owned cell's mask word (the cell is the upper tap row's voxel of this lane's
@@ -743,14 +755,17 @@ __device__ __forceinline__ void grad_shift_tile(
     };
     auto sample = [&](int z, const Taps2& f) {
         const float4 wt = s_w[wv][z];
+        const float4 a0 = Vox<DT>::decode(f.t00), a1 = Vox<DT>::decode(f.t01);
         float4 s;
-        s.x = lerp_taps(f.t00.x, f.t01.x, wt);
-        s.y = lerp_taps(f.t00.y, f.t01.y, wt);
-        s.z = lerp_taps(f.t00.z, f.t01.z, wt);
-        s.w = lerp_taps(f.t00.w, f.t01.w, wt);
+        s.x = lerp_taps(a0.x, a1.x, wt);
+        s.y = lerp_taps(a0.y, a1.y, wt);
+        s.z = lerp_taps(a0.z, a1.z, wt);
+        s.w = lerp_taps(a0.w, a1.w, wt);
         return s;
     };
-    constexpr int kAhead = 2;
+    // planes of taps in flight: BF16 taps stay as stored (half the registers) until used,
+    // which leaves room for a third plane; FP32 taps fill the same registers with two
+    constexpr int kAhead = DT == HSGD_BF16 ? 3 : 2;
     // Every plane iteration starts with a branch on an opaque, always-true value: the block
     // boundaries keep the compiler from moving each plane's setup code across planes (which
     // would keep all of it alive at once).
@@ -808,9 +823,11 @@ __device__ __forceinline__ void grad_shift_tile(
         // each is issued before its plane's branch rather than sunk to its use two planes
         // later. Up to 32 planes that hides the load latency; with 64 planes (4 waves per
         // SIMD with or without it) it measured slower, so there the loads sink to their use.
-        if constexpr (MAXD <= 32)
-            asm volatile("" ::"v"(q[0].t00.x), "v"(q[0].t01.x), "v"((uint32_t)qm[0]), "v"(q[1].t00.x),
-                         "v"(q[1].t01.x), "v"((uint32_t)qm[1]));
+        if constexpr (MAXD <= 32) {
+#pragma unroll
+            for (int i = 0; i < kAhead; ++i)
+                asm volatile("" ::"v"(q[i].t00.x), "v"(q[i].t01.x), "v"((uint32_t)qm[i]));
+        }
     }
     // planes where the wave below has selected cells: it needs this wave's adjoints
     if (lane == 0) s_bits[wv] = own_bits;
@@ -913,8 +930,10 @@ __device__ __forceinline__ void grad_shift_tile(
             }
             __builtin_amdgcn_sched_barrier(0);
         }
-        if constexpr (MAXD <= 32)
-            asm volatile("" ::"v"(q[0].t00.x), "v"(q[0].t01.x), "v"(q[1].t00.x), "v"(q[1].t01.x));
+        if constexpr (MAXD <= 32) {
+#pragma unroll
+            for (int i = 0; i < kAhead; ++i) asm volatile("" ::"v"(q[i].t00.x), "v"(q[i].t01.x));
+        }
     }
     if (partials) {
         const float tot = block_sum(sq, sred);
