@@ -205,18 +205,26 @@ hsgd_status refine_run(const char* fn, hsgd_mpi* levels, const hsgd_views* views
     const int N = views[0].N;
     const RefineWs R = refine_ws(top.D, top.H, top.W, N, sel.k, L);
 
-    // target pyramid: coarser images that were not given are box means of the finer ones
+    // target pyramid: coarser images that were not given are box means of the finer ones,
+    // up to three consecutive missing levels from one launch
     const float* img[16];
     img[L - 1] = views[L - 1].images;
-    for (int l = L - 2; l >= 0; --l) {
+    for (int l = L - 2; l >= 0;) {
         if (views[l].images) {
             img[l] = views[l].images;
+            --l;
             continue;
         }
-        float* dst = reinterpret_cast<float*>((char*)ws + R.pyr_off[l]);
-        int e = launch_downsample(img[l + 1], N, levels[l + 1].H, levels[l + 1].W, dst, stream);
+        int nl = 0;
+        float* dst[3] = {nullptr, nullptr, nullptr};
+        while (nl < 3 && l - nl >= 0 && !views[l - nl].images) {
+            dst[nl] = reinterpret_cast<float*>((char*)ws + R.pyr_off[l - nl]);
+            ++nl;
+        }
+        int e = launch_pyramid(img[l + 1], N, levels[l + 1].H, levels[l + 1].W, nl, dst, stream);
         if (e) return hip_status(e, fn);
-        img[l] = dst;
+        for (int j = 0; j < nl; ++j) img[l - j] = dst[j];
+        l -= nl;
     }
     // one mask and one workspace region sized for the finest level serve every level
     uint64_t* mask = reinterpret_cast<uint64_t*>((char*)ws + R.mask_off);

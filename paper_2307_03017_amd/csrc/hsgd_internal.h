@@ -130,6 +130,9 @@ int launch_upsample(const hsgd_mpi& coarse, const hsgd_mpi& fine, hipStream_t s)
 // upsampling into `fine` fused with the selection on the stored result (mask [H][W])
 int launch_upsample_select(const hsgd_mpi& coarse, const hsgd_mpi& fine, int k, float tau, int rule, uint64_t* mask,
                            hipStream_t s);
+// nl (1..3) successive 2x2 box means of [N][H][W][3] images in one launch: out[j] receives
+// level j + 1 below the input (H and W multiples of 2^nl).
+int launch_pyramid(const float* img, int N, int H, int W, int nl, float* const* out, hipStream_t s);
 int launch_downsample(const float* img, int N, int H, int W, float* out, hipStream_t s);
 // plane-sweep volume levels 0..L-1 ([N][D][H>>l][W>>l][3] FP32 or BF16; out[l] NULL: not stored)
 constexpr int kPsvMaxL = 5;

@@ -9,8 +9,11 @@
 //  k_grad       forward scan, residual, back-to-front adjoint scan, transposed bilinear
 //               scatter restricted to S (Sec. 3.3; Eq. 4 gradient)
 //  k_update     restore the sparse step onto S with clamp (the M_{n+1} update)
-//  k_upsample   2x bilinear MPI upsampling between hierarchy levels
-//  k_downsample 2x2 box mean of target images (the H/2^l pyramid, Sec. 3.2)
+//  k_upsample   2x bilinear MPI upsampling between hierarchy levels; k_upsample_select(_blk)
+//               fuse it with the new level's first selection (per output pixel on small
+//               levels, per 2 x 2 output block from three source rows on large ones)
+//  k_downsample 2x2 box mean of target images (the H/2^l pyramid, Sec. 3.2); k_pyramid
+//               computes up to three such levels from one read of the finer images
 #include <hip/hip_runtime.h>
 
 #include "hsgd_device.h"
@@ -36,6 +39,11 @@ struct Vox<HSGD_FP32> {
     }
     static __device__ __forceinline__ void store(void* base, int i, float4 v) {
         reinterpret_cast<float4*>(base)[i] = v;
+    }
+    // voxels i and i + 1 (i even)
+    static __device__ __forceinline__ void store2(void* base, int i, float4 a, float4 b) {
+        reinterpret_cast<float4*>(base)[i] = a;
+        reinterpret_cast<float4*>(base)[i + 1] = b;
     }
     // voxel `col` of the row starting at `row` (row uniform across the wave)
     static __device__ __forceinline__ float4 load_row(const char* row, unsigned col) {
@@ -72,6 +80,15 @@ struct Vox<HSGD_BF16> {
         r.x = f32_to_bf16_bits(v.x) | (f32_to_bf16_bits(v.y) << 16);
         r.y = f32_to_bf16_bits(v.z) | (f32_to_bf16_bits(v.w) << 16);
         reinterpret_cast<uint2*>(base)[i] = r;
+    }
+    // voxels i and i + 1 (i even: one 16-byte store)
+    static __device__ __forceinline__ void store2(void* base, int i, float4 a, float4 b) {
+        uint4 r;
+        r.x = f32_to_bf16_bits(a.x) | (f32_to_bf16_bits(a.y) << 16);
+        r.y = f32_to_bf16_bits(a.z) | (f32_to_bf16_bits(a.w) << 16);
+        r.z = f32_to_bf16_bits(b.x) | (f32_to_bf16_bits(b.y) << 16);
+        r.w = f32_to_bf16_bits(b.z) | (f32_to_bf16_bits(b.w) << 16);
+        reinterpret_cast<uint4*>(base)[i >> 1] = r;
     }
     static __device__ __forceinline__ float4 load_row(const char* row, unsigned col) {
         const uint2 r = *reinterpret_cast<const uint2*>(row + (col << 3));
@@ -1187,33 +1204,55 @@ __global__ __launch_bounds__(256) void k_update(void* __restrict__ mpi, int D, i
 // ------------------------------------------------------------------------------------
 // hierarchy
 // ------------------------------------------------------------------------------------
-// Output voxel i of plane z of the 2x upsampling of a [D][h][w] level.
-// The four source taps of output voxel i of a 2x upsampling (plane base z*h*w of the
-// source) and their weights.
+// Source pair and fraction of output coordinate x of a 2x upsampling along an axis of n
+// source samples: the sample point (x + 1/2) / 2 - 1/2, clamped to [0, n - 1].
+__device__ __forceinline__ void up_axis(int x, int n, int& i0, int& i1, float& f) {
+    const float sx = fminf(fmaxf((x + 0.5f) * 0.5f - 0.5f, 0.0f), (float)(n - 1));
+    i0 = (int)sx;
+    i1 = min(i0 + 1, n - 1);
+    f = sx - i0;
+}
+
+struct UpW {
+    float w00, w10, w01, w11;
+};
+__device__ __forceinline__ UpW up_weights(float fx, float fy) {
+    return UpW{(1 - fx) * (1 - fy), fx * (1 - fy), (1 - fx) * fy, fx * fy};
+}
+// The bilinear blend of taps a (x0, y0), b (x1, y0), c (x0, y1), d (x1, y1): the one
+// expression every upsampling path evaluates, so that they agree bit for bit.
+__device__ __forceinline__ float4 up_blend(const UpW& w, const float4& a, const float4& b, const float4& c,
+                                           const float4& d) {
+    float4 o;
+    o.x = w.w00 * a.x + w.w10 * b.x + w.w01 * c.x + w.w11 * d.x;
+    o.y = w.w00 * a.y + w.w10 * b.y + w.w01 * c.y + w.w11 * d.y;
+    o.z = w.w00 * a.z + w.w10 * b.z + w.w01 * c.z + w.w11 * d.z;
+    o.w = w.w00 * a.w + w.w10 * b.w + w.w01 * c.w + w.w11 * d.w;
+    return o;
+}
+
+// The four source taps of output voxel i of plane z of the 2x upsampling of a [D][h][w]
+// level, and their weights.
 template <int DT>
 struct UpTaps {
     float4 a, b, c, d;
-    float w00, w10, w01, w11;
+    UpW w;
 };
 template <int DT>
 __device__ __forceinline__ UpTaps<DT> upsample_taps(const void* __restrict__ src, int h, int w, int z, int i) {
     const int W2 = 2 * w;
     const int x = i % W2, y = i / W2;
-    const float sx = fminf(fmaxf((x + 0.5f) * 0.5f - 0.5f, 0.0f), (float)(w - 1));
-    const float sy = fminf(fmaxf((y + 0.5f) * 0.5f - 0.5f, 0.0f), (float)(h - 1));
-    const int x0 = (int)sx, y0 = (int)sy;
-    const int x1 = min(x0 + 1, w - 1), y1 = min(y0 + 1, h - 1);
-    const float fx = sx - x0, fy = sy - y0;
+    int x0, x1, y0, y1;
+    float fx, fy;
+    up_axis(x, w, x0, x1, fx);
+    up_axis(y, h, y0, y1, fy);
     const int base = z * h * w;
     UpTaps<DT> t;
     t.a = Vox<DT>::load(src, base + y0 * w + x0);
     t.b = Vox<DT>::load(src, base + y0 * w + x1);
     t.c = Vox<DT>::load(src, base + y1 * w + x0);
     t.d = Vox<DT>::load(src, base + y1 * w + x1);
-    t.w00 = (1 - fx) * (1 - fy);
-    t.w10 = fx * (1 - fy);
-    t.w01 = (1 - fx) * fy;
-    t.w11 = fx * fy;
+    t.w = up_weights(fx, fy);
     return t;
 }
 
@@ -1222,11 +1261,7 @@ __device__ __forceinline__ UpTaps<DT> upsample_taps(const void* __restrict__ src
 template <int DT>
 __device__ __forceinline__ float4 upsample_store(const UpTaps<DT>& t, void* __restrict__ dst, int H2W2, int z,
                                                  int i) {
-    float4 o;
-    o.x = t.w00 * t.a.x + t.w10 * t.b.x + t.w01 * t.c.x + t.w11 * t.d.x;
-    o.y = t.w00 * t.a.y + t.w10 * t.b.y + t.w01 * t.c.y + t.w11 * t.d.y;
-    o.z = t.w00 * t.a.z + t.w10 * t.b.z + t.w01 * t.c.z + t.w11 * t.d.z;
-    o.w = t.w00 * t.a.w + t.w10 * t.b.w + t.w01 * t.c.w + t.w11 * t.d.w;
+    const float4 o = up_blend(t.w, t.a, t.b, t.c, t.d);
     Vox<DT>::store(dst, z * H2W2 + i, o);
     return Vox<DT>::stored(o);
 }
@@ -1246,13 +1281,15 @@ __global__ __launch_bounds__(256) void k_upsample(const void* __restrict__ src, 
     upsample_voxel<DT>(src, h, w, dst, blockIdx.y, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// Upsampling fused with the first selection at the new level. A block covers 64 output
-// pixels (lane = pixel) and its four waves split the planes: each upsamples and stores a
+constexpr int kUpWaves = 4;
+
+// Upsampling fused with the first selection at the new level, for levels of few
+// workgroups. A block covers 64 output pixels (lane = pixel) and its four waves split the
+// planes: each upsamples and stores a
 // quarter of them and puts the alpha it stored (the storage-rounded value) in LDS; the
 // first wave then scores every plane of its pixel front to back and writes the mask, which
 // equals what k_select computes from the stored level. Splitting the planes shortens each
 // thread's chain of dependent tap loads and gives the small levels four times the waves.
-constexpr int kUpWaves = 4;
 template <int DT, int MAXD>
 __global__ __launch_bounds__(64 * kUpWaves) void k_upsample_select(const void* __restrict__ src, int D, int h,
                                                                    int w, void* __restrict__ dst, int k,
@@ -1291,6 +1328,164 @@ __global__ __launch_bounds__(64 * kUpWaves) void k_upsample_select(const void* _
     }
 }
 
+// Upsampling fused with the first selection at the new level, for large levels. A
+// workgroup takes one source row Y and 62 source columns (lane = source column X = X0 - 1 + lane; lanes 0 and 63 only
+// supply taps to their neighbours) and writes the 2 x 2 output voxels of each of its owner
+// columns: per plane it loads source rows Y - 1, Y and Y + 1 (clamped) of its column and
+// takes the columns X - 1 and X + 1 from the neighbouring lanes, so a loaded voxel serves
+// four outputs. The taps, weights and blend of every output are those of upsample_taps
+// (the same source voxels, the same expression). The four waves split the planes and put
+// the alpha they stored (storage-rounded) in LDS; then each wave scores and selects a
+// quarter of the 248 output pixels front to back, as k_select does on the stored level.
+constexpr int kUpCols = 62;               // owner source columns per workgroup
+// Below this many workgroups (8 per CU) the 2 x 2 kernel has too few waves to hide its
+// longer per-wave work, and the per-pixel kernel is the faster one.
+constexpr int64_t kUpBlkMinGroups = 2048;
+constexpr int kUpPix = 4 * kUpCols;       // output pixels per workgroup (2 rows x 124)
+
+// alpha as the selection reads it back from LDS: FP32, or the stored BF16 bits (exact)
+template <int DT>
+struct UpAlpha {
+    using T = float;
+    static __device__ __forceinline__ T put(float a) { return a; }
+    static __device__ __forceinline__ float get(T v) { return v; }
+};
+template <>
+struct UpAlpha<HSGD_BF16> {
+    using T = uint16_t;
+    static __device__ __forceinline__ T put(float a) { return (uint16_t)(__float_as_uint(a) >> 16); }
+    static __device__ __forceinline__ float get(T v) { return __uint_as_float((uint32_t)v << 16); }
+};
+
+__device__ __forceinline__ float4 lane_prev4(const float4& v) {
+    return make_float4(lane_from_prev(v.x), lane_from_prev(v.y), lane_from_prev(v.z), lane_from_prev(v.w));
+}
+__device__ __forceinline__ float4 lane_next4(const float4& v) {
+    return make_float4(lane_from_next(v.x), lane_from_next(v.y), lane_from_next(v.z), lane_from_next(v.w));
+}
+__device__ __forceinline__ float4 pick4(bool c, const float4& a, const float4& b) {
+    return make_float4(c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z, c ? a.w : b.w);
+}
+
+template <int DT, int MAXD>
+__global__ __launch_bounds__(64 * kUpWaves) void k_upsample_select_blk(const void* __restrict__ src, int D, int h,
+                                                                       int w, void* __restrict__ dst, int k,
+                                                                       float tau, int rule,
+                                                                       uint64_t* __restrict__ mask) {
+    constexpr int kPW = (MAXD + kUpWaves - 1) / kUpWaves;   // planes per wave
+    constexpr int kG = kPW < 4 ? kPW : 4;                    // planes of loads in flight
+    static_assert(kPW % kG == 0, "whole load groups");
+    using AT = typename UpAlpha<DT>::T;
+    __shared__ AT s_a[MAXD][kUpPix];
+    const int lane = threadIdx.x & 63;
+    const int q = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int Y = blockIdx.y;
+    const int X = (int)blockIdx.x * kUpCols - 1 + lane;
+    const int Xc = min(max(X, 0), w - 1);
+    const bool own = lane >= 1 && lane <= kUpCols && X < w;
+    const int hw = h * w, W2 = 2 * w, n = 4 * hw;
+    const int row0 = max(Y - 1, 0) * w + Xc, row1 = Y * w + Xc, row2 = min(Y + 1, h - 1) * w + Xc;
+    // Output column 2X + a and row 2Y + b take source columns / rows x0, x1 / y0, y1 (up_axis).
+    // For an owner column these are X - 1 or X (x0, a = 0), X or X + 1 (x1, a = 0), X
+    // (x0, a = 1), X + 1 or X (x1, a = 1), and likewise for the rows: the flags below say
+    // which, and a neighbour's column is always inside the level when it is used.
+    bool xl0, xr0, xr1, yu0, yd0, yd1;
+    UpW wt[2][2];
+    {
+        int i0, i1, j0, j1;
+        float fx[2], fy[2];
+        up_axis(2 * X, w, i0, i1, fx[0]);
+        xl0 = i0 < X;
+        xr0 = i1 > X;
+        up_axis(2 * X + 1, w, i0, i1, fx[1]);
+        xr1 = i1 > X;
+        up_axis(2 * Y, h, j0, j1, fy[0]);
+        yu0 = j0 < Y;
+        yd0 = j1 > Y;
+        up_axis(2 * Y + 1, h, j0, j1, fy[1]);
+        yd1 = j1 > Y;
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) wt[b][a] = up_weights(fx[a], fy[b]);
+    }
+    // a wave whose owner columns and row are all inside the level (taps X - 1, X, X + 1 and
+    // Y - 1, Y, Y + 1, as for every column and row but the first and last) skips the picks
+    const bool inner = __builtin_amdgcn_ballot_w64(own && !(xl0 && !xr0 && xr1)) == 0 && yu0 && !yd0 && yd1;
+    const int out0 = 2 * Y * W2 + 2 * X;    // output voxel (2Y, 2X) of plane 0
+    const int pix = 2 * (lane - 1);         // LDS column of output pixel (2Y, 2X)
+#pragma unroll
+    for (int j0 = 0; j0 < kPW; j0 += kG) {
+        float4 m[kG][3];
+#pragma unroll
+        for (int j = 0; j < kG; ++j) {
+            // plane index clamped, so the loads need no guard
+            const int base = min(q * kPW + j0 + j, D - 1) * hw;
+            m[j][0] = Vox<DT>::load(src, base + row0);
+            m[j][1] = Vox<DT>::load(src, base + row1);
+            m[j][2] = Vox<DT>::load(src, base + row2);
+        }
+#pragma unroll
+        for (int j = 0; j < kG; ++j) {
+            const int z = q * kPW + j0 + j;
+            float4 L[3], R[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                L[r] = lane_prev4(m[j][r]);
+                R[r] = lane_next4(m[j][r]);
+            }
+            float4 o00, o01, o10, o11;
+            if (inner) {
+                o00 = up_blend(wt[0][0], L[0], m[j][0], L[1], m[j][1]);
+                o01 = up_blend(wt[0][1], m[j][0], R[0], m[j][1], R[1]);
+                o10 = up_blend(wt[1][0], L[1], m[j][1], L[2], m[j][2]);
+                o11 = up_blend(wt[1][1], m[j][1], R[1], m[j][2], R[2]);
+            } else {
+                // per source row r: the taps of columns x0 / x1 for a = 0 and x1 for a = 1
+                float4 c00[3], c01[3], c11[3];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    c00[r] = pick4(xl0, L[r], m[j][r]);
+                    c01[r] = pick4(xr0, R[r], m[j][r]);
+                    c11[r] = pick4(xr1, R[r], m[j][r]);
+                }
+                // rows y0 / y1: b = 0 takes rows (0 or 1) and (1 or 2), b = 1 rows 1 and (2 or 1)
+                o00 = up_blend(wt[0][0], yu0 ? c00[0] : c00[1], yu0 ? c01[0] : c01[1], yd0 ? c00[2] : c00[1],
+                               yd0 ? c01[2] : c01[1]);
+                o01 = up_blend(wt[0][1], yu0 ? m[j][0] : m[j][1], yu0 ? c11[0] : c11[1], yd0 ? m[j][2] : m[j][1],
+                               yd0 ? c11[2] : c11[1]);
+                o10 = up_blend(wt[1][0], c00[1], c01[1], yd1 ? c00[2] : c00[1], yd1 ? c01[2] : c01[1]);
+                o11 = up_blend(wt[1][1], m[j][1], c11[1], yd1 ? m[j][2] : m[j][1], yd1 ? c11[2] : c11[1]);
+            }
+            if (own && z < D) {
+                Vox<DT>::store2(dst, z * n + out0, o00, o01);
+                Vox<DT>::store2(dst, z * n + out0 + W2, o10, o11);
+                s_a[z][pix] = UpAlpha<DT>::put(Vox<DT>::stored(o00).w);
+                s_a[z][pix + 1] = UpAlpha<DT>::put(Vox<DT>::stored(o01).w);
+                s_a[z][kUpPix / 2 + pix] = UpAlpha<DT>::put(Vox<DT>::stored(o10).w);
+                s_a[z][kUpPix / 2 + pix + 1] = UpAlpha<DT>::put(Vox<DT>::stored(o11).w);
+            }
+        }
+    }
+    __syncthreads();
+    // selection: output pixel e of the workgroup (row 2Y + e / 124, column 2 X0 + e % 124)
+    const int e = q * 64 + lane;
+    const int ox = 2 * (int)blockIdx.x * kUpCols + e % (kUpPix / 2);
+    if (e < kUpPix && ox < W2) {
+        const int oy = 2 * Y + e / (kUpPix / 2);
+        float A[MAXD];
+        float T = 1.0f;
+#pragma unroll
+        for (int z = 0; z < MAXD; ++z)
+            if (z < D) A[z] = score_step(UpAlpha<DT>::get(s_a[z][e]), T);
+        mask[oy * W2 + ox] = topk_bits<MAXD>(A, D, k, tau, rule);
+    }
+}
+
+// The 2x2 box mean of a (x, y), b (x + 1, y), c (x, y + 1), d (x + 1, y + 1): the one
+// expression every downsampling path evaluates.
+__device__ __forceinline__ float box4(float a, float b, float c, float d) { return ((a + b) + (c + d)) * 0.25f; }
+
 // Output pixel i of view n of the 2x2 box mean of [N][H][W][3] images.
 __device__ __forceinline__ void downsample_pixel(const float* __restrict__ img, int H, int W,
                                                  float* __restrict__ out, int n, int i) {
@@ -1299,8 +1494,58 @@ __device__ __forceinline__ void downsample_pixel(const float* __restrict__ img, 
     const int x = i % w, y = i / w;
     const float* s = img + ((size_t)n * H + 2 * y) * W * 3 + 6 * x;
     float* o = out + ((size_t)n * h * w + i) * 3;
-    for (int c = 0; c < 3; ++c)
-        o[c] = ((s[c] + s[3 + c]) + (s[3 * W + c] + s[3 * W + 3 + c])) * 0.25f;
+    for (int c = 0; c < 3; ++c) o[c] = box4(s[c], s[3 + c], s[3 * W + c], s[3 * W + 3 + c]);
+}
+
+// NL successive 2x2 box means of [N][H][W][3] images (H and W multiples of 2^NL) in one
+// launch: a thread takes one pixel of the coarsest result, reads its 2^NL x 2^NL block once
+// and writes its share of every level (out[j]: level j + 1), each level the box means of
+// the one above as downsample_pixel computes them.
+template <int NL>
+__global__ __launch_bounds__(256) void k_pyramid(const float* __restrict__ img, int H, int W,
+                                                 float* __restrict__ out0, float* __restrict__ out1,
+                                                 float* __restrict__ out2) {
+    constexpr int S = 1 << NL;
+    const int n = blockIdx.y;
+    const int hc = H >> NL, wc = W >> NL;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= hc * wc) return;
+    const int x = i % wc, y = i / wc;
+    float cur[S / 2][S / 2][3];
+#pragma unroll
+    for (int r = 0; r < S / 2; ++r) {
+        const float* s0 = img + (((size_t)n * H + y * S + 2 * r) * W + (size_t)x * S) * 3;
+        const float* s1 = s0 + (size_t)W * 3;
+#pragma unroll
+        for (int c = 0; c < S / 2; ++c)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch)
+                cur[r][c][ch] = box4(s0[6 * c + ch], s0[6 * c + 3 + ch], s1[6 * c + ch], s1[6 * c + 3 + ch]);
+    }
+    float* const outs[3] = {out0, out1, out2};
+#pragma unroll
+    for (int l = 1; l <= NL; ++l) {
+        const int E = S >> l;                       // this thread's block edge at level l
+        const int Hl = H >> l, Wl = W >> l;
+        float* o = outs[l - 1];
+#pragma unroll
+        for (int r = 0; r < E; ++r)
+#pragma unroll
+            for (int c = 0; c < E; ++c)
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch)
+                    o[(((size_t)n * Hl + y * E + r) * Wl + (size_t)x * E + c) * 3 + ch] = cur[r][c][ch];
+        if (l < NL) {
+#pragma unroll
+            for (int r = 0; r < E / 2; ++r)
+#pragma unroll
+                for (int c = 0; c < E / 2; ++c)
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch)
+                        cur[r][c][ch] = box4(cur[2 * r][2 * c][ch], cur[2 * r][2 * c + 1][ch],
+                                             cur[2 * r + 1][2 * c][ch], cur[2 * r + 1][2 * c + 1][ch]);
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_downsample(const float* __restrict__ img, int H, int W,
@@ -1557,11 +1802,31 @@ int launch_upsample(const hsgd_mpi& c, const hsgd_mpi& f, hipStream_t s) {
 
 int launch_upsample_select(const hsgd_mpi& c, const hsgd_mpi& f, int k, float tau, int rule, uint64_t* mask,
                            hipStream_t s) {
-    const dim3 grid((unsigned)ceil_div((int64_t)f.H * f.W, 64));
     ProfScope ps(HSGD_K_UPSAMPLE, s);
-    HSGD_DISPATCH_T(c.dtype, HSGD_DISPATCH_D(c.D, hipLaunchKernelGGL((k_upsample_select<DT, MD>), grid, dim3(64 * kUpWaves), 0, s,
-                                                                    c.rgba, c.D, c.H, c.W, f.rgba, k, tau, rule,
-                                                                    mask)));
+    const dim3 blk((unsigned)ceil_div(c.W, kUpCols), (unsigned)c.H);
+    if ((int64_t)blk.x * blk.y >= kUpBlkMinGroups) {
+        HSGD_DISPATCH_T(c.dtype, HSGD_DISPATCH_D(c.D, hipLaunchKernelGGL((k_upsample_select_blk<DT, MD>), blk,
+                                                                        dim3(64 * kUpWaves), 0, s, c.rgba, c.D, c.H,
+                                                                        c.W, f.rgba, k, tau, rule, mask)));
+    } else {
+        const dim3 grid((unsigned)ceil_div((int64_t)f.H * f.W, 64));
+        HSGD_DISPATCH_T(c.dtype, HSGD_DISPATCH_D(c.D, hipLaunchKernelGGL((k_upsample_select<DT, MD>), grid,
+                                                                        dim3(64 * kUpWaves), 0, s, c.rgba, c.D, c.H,
+                                                                        c.W, f.rgba, k, tau, rule, mask)));
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_pyramid(const float* img, int N, int H, int W, int nl, float* const* out, hipStream_t s) {
+    const int hc = H >> nl, wc = W >> nl;
+    const dim3 grid((unsigned)ceil_div((int64_t)hc * wc, 256), (unsigned)N);
+    ProfScope ps(HSGD_K_DOWNSAMPLE, s);
+    if (nl == 1)
+        hipLaunchKernelGGL(k_pyramid<1>, grid, dim3(256), 0, s, img, H, W, out[0], nullptr, nullptr);
+    else if (nl == 2)
+        hipLaunchKernelGGL(k_pyramid<2>, grid, dim3(256), 0, s, img, H, W, out[0], out[1], nullptr);
+    else
+        hipLaunchKernelGGL(k_pyramid<3>, grid, dim3(256), 0, s, img, H, W, out[0], out[1], out[2]);
     return (int)hipGetLastError();
 }
 

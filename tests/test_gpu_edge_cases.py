@@ -168,19 +168,25 @@ def test_refine_with_no_iterations_only_upsamples():
     assert np.abs(out.cpu().numpy() - O.upsample2x(M0)).max() <= 1e-6
 
 
-@pytest.mark.parametrize("D, k, rule, quant, dtype", [
-    (32, 4, "topk", False, torch.float32),
-    (13, 5, "topk", True, torch.float32),       # exact ties in the scores
-    (8, 6, "topk", True, torch.float32),        # k > D/2: the passes that drop the worst
-    (32, 4, "mvs", True, torch.bfloat16),
-    (64, 3, "topk", False, torch.bfloat16),     # every bit of the mask word
+@pytest.mark.parametrize("D, k, rule, quant, dtype, W, H", [
+    (32, 4, "topk", False, torch.float32, 64, 32),
+    (13, 5, "topk", True, torch.float32, 64, 32),       # exact ties in the scores
+    (8, 6, "topk", True, torch.float32, 64, 32),        # k > D/2: the passes that drop the worst
+    (32, 4, "mvs", True, torch.bfloat16, 64, 32),
+    (64, 3, "topk", False, torch.bfloat16, 64, 32),     # every bit of the mask word
+    (16, 3, "topk", True, torch.float32, 260, 42),      # three column tiles, the last ragged
+    (32, 4, "topk", False, torch.bfloat16, 250, 6),     # ragged tiles, a 3-row source level
+    (7, 2, "topk", False, torch.float32, 4, 4),         # a 2 x 2 source level: every column a border
+    # source levels of >= 2048 workgroups of 62 columns x 1 row: the 2 x 2 kernel
+    (8, 3, "topk", True, torch.float32, 2010, 260),     # ragged last column tile
+    (16, 4, "mvs", False, torch.bfloat16, 2048, 256),
 ], ids=lambda v: str(v).replace("torch.", ""))
-def test_level_transition_selects_like_select_active(D, k, rule, quant, dtype):
+def test_level_transition_selects_like_select_active(D, k, rule, quant, dtype, W, H):
     """The level transition fuses the 2x upsampling with the new level's first selection. A
     two-level refine that spends its only iteration on the finer level must equal, bit for
     bit, the upsampling, hsgd_select_active on the stored level and one hsgd_grad_step on
     that mask with the same rates (quantised alphas put exact ties into the scores)."""
-    W, H, N, f = 64, 32, 3, 40.0
+    N, f = 3, 40.0
     rng = np.random.default_rng(80 + D)
     rg = shift_rig(W, H, D, f, rng.uniform(-0.05, 0.05, size=(N, 2)))
     M0 = rng.uniform(0.05, 0.95, size=(D, H // 2, W // 2, 4))
@@ -189,7 +195,7 @@ def test_level_transition_selects_like_select_active(D, k, rule, quant, dtype):
     M0d = to_dev(M0, dtype)
     I = to_dev(rng.uniform(size=(N, H, W, 3)))
     lr_rgb, lr_a = 0.7, 0.9
-    print(f"level transition D={D} k={k} rule={rule} {dtype}", flush=True)
+    print(f"level transition D={D} k={k} rule={rule} {dtype} {W}x{H}", flush=True)
     out, losses = hsgd.hsgd_refine(M0d, I, rg["K_ref"], rg["K"], rg["R"], rg["t"], rg["depths"], (0, 1), k,
                                    lr_rgb=lr_rgb, lr_alpha=lr_a, rule=rule)
     up = hsgd.hsgd_upsample2x(M0d)
@@ -199,3 +205,28 @@ def test_level_transition_selects_like_select_active(D, k, rule, quant, dtype):
     torch.cuda.synchronize()
     assert torch.equal(out, up)
     assert losses.numel() == 1 and abs(losses.item() - loss.item()) <= 1e-6 * loss.item()
+
+
+def test_refine_target_pyramid_equals_chained_downsampling():
+    """The refine builds the missing coarser targets with one fused launch per run of up to
+    three levels. Given every level (each the 2x2 box means of the one above, from
+    hsgd_downsample2x), none, or only some of them, the refine must come out the same, bit
+    for bit: the fused pyramid computes what chained downsampling does."""
+    sc = scenes.make_scene("c2", levels=4, iters=(1, 1, 1, 1))
+    rng = np.random.default_rng(91)
+    targets = to_dev(rng.uniform(size=(sc.N, sc.H, sc.W, 3)))
+    chain = [targets]
+    for _ in range(3):
+        chain.insert(0, hsgd.hsgd_downsample2x(chain[0]))
+    init = to_dev(sc.initial_mpi())
+    plan = hsgd.RefinePlan(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths, sc.W, sc.H,
+                           sc.iters, sc.k)
+    results = []
+    for given in ([None, None, None], chain[:3], [None, chain[1], None], [chain[0], None, None]):
+        plan.levels[0].copy_(init)
+        plan.run(targets, descriptors=plan.descriptors(targets, given))
+        torch.cuda.synchronize()
+        results.append((plan.levels[-1].clone(), plan.loss_log[:4].clone()))
+    for out, losses in results[1:]:
+        assert torch.equal(out, results[0][0])
+        assert torch.equal(losses, results[0][1])
