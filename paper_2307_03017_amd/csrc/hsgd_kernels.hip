@@ -418,9 +418,9 @@ __global__ __launch_bounds__(kBlock) void k_render(const void* __restrict__ mpi,
             const Taps tp = make_taps(sw[z], x, y, H, W);
             const float4 s = sample<DT>(mpi, z * HW, tp);
             const float wgt = T * s.w;
-            c0 += wgt * s.x;
-            c1 += wgt * s.y;
-            c2 += wgt * s.z;
+            c0 = __builtin_fmaf(wgt, s.x, c0);
+            c1 = __builtin_fmaf(wgt, s.y, c1);
+            c2 = __builtin_fmaf(wgt, s.z, c2);
             T *= 1.0f - s.w;
         }
         const size_t pix = ((size_t)view * H + y) * W + x;
@@ -433,7 +433,7 @@ __global__ __launch_bounds__(kBlock) void k_render(const void* __restrict__ mpi,
             const float d0 = c0 - images[3 * pix + 0];
             const float d1 = c1 - images[3 * pix + 1];
             const float d2 = c2 - images[3 * pix + 2];
-            sq = d0 * d0 + d1 * d1 + d2 * d2;
+            sq = __builtin_fmaf(d2, d2, __builtin_fmaf(d1, d1, d0 * d0));
         }
     }
     if (partials) {
@@ -536,9 +536,9 @@ __global__ __launch_bounds__(kBlock) void k_grad(const void* __restrict__ mpi, i
             const float4 s = sample<DT>(mpi, z * HW, tp);
             Ts[z] = T;
             const float wgt = T * s.w;
-            c0 += wgt * s.x;
-            c1 += wgt * s.y;
-            c2 += wgt * s.z;
+            c0 = __builtin_fmaf(wgt, s.x, c0);
+            c1 = __builtin_fmaf(wgt, s.y, c1);
+            c2 = __builtin_fmaf(wgt, s.z, c2);
             T *= 1.0f - s.w;
         }
     }
@@ -549,7 +549,7 @@ __global__ __launch_bounds__(kBlock) void k_grad(const void* __restrict__ mpi, i
             const float d0 = c0 - images[3 * pix + 0];
             const float d1 = c1 - images[3 * pix + 1];
             const float d2 = c2 - images[3 * pix + 2];
-            sq = d0 * d0 + d1 * d1 + d2 * d2;
+            sq = __builtin_fmaf(d2, d2, __builtin_fmaf(d1, d1, d0 * d0));
             g0 = d0 * inv_n;
             g1 = d1 * inv_n;
             g2 = d2 * inv_n;
@@ -665,7 +665,21 @@ __device__ __forceinline__ float lerp_taps(float a0, float a1, const float4& wt)
 
 // One 64 x 8 tile of one view (tile = view + N * (tx + ntx * ty)); every thread of the
 // workgroup calls it.
-template <int DT, int MAXD, bool MASKED>
+// Planes whose front-to-back samples the gradient tile keeps for its back-to-front scan,
+// and the waves per SIMD the kernel is compiled for: up to 32 planes 6 (3 workgroups per CU,
+// within 80 registers), except FP32 at 32 planes, which keeps the samples of its last 12
+// planes in the registers of 4 waves per SIMD (2 workgroups per CU) and measured faster;
+// 64 planes run at 4 waves per SIMD without a register bound.
+template <int DT, int MAXD>
+constexpr int grad_shift_keep() {
+    return DT == HSGD_FP32 && MAXD == 32 ? 12 : 0;
+}
+template <int DT, int MAXD>
+constexpr int grad_shift_waves() {
+    return MAXD > 32 ? 1 : (grad_shift_keep<DT, MAXD>() > 0 ? 4 : 6);
+}
+
+template <int DT, int MAXD, bool MASKED, int KEEP = grad_shift_keep<DT, MAXD>()>
 __device__ __forceinline__ void grad_shift_tile(
     const void* __restrict__ mpi, int D, int H, int W, int N, const hsgd_warp* __restrict__ warps,
     const float* __restrict__ images, const float* __restrict__ dimg, const uint64_t* __restrict__ mask,
@@ -783,6 +797,11 @@ __device__ __forceinline__ void grad_shift_tile(
     // planes of taps in flight: BF16 taps stay as stored (half the registers) until used,
     // which leaves room for a third plane; FP32 taps fill the same registers with two
     constexpr int kAhead = DT == HSGD_BF16 ? 3 : 2;
+    // The samples of the last kKeep planes of the front-to-back scan stay in registers for
+    // the back-to-front scan, which starts with them: 2 kKeep fewer row loads per wave (FP32
+    // at 32 planes; the kernel then runs at 4 waves per SIMD, see grad_shift_waves).
+    constexpr int kKeep = KEEP;
+    float4 Sk[kKeep > 0 ? kKeep : 1];
     // Every plane iteration starts with a branch on an opaque, always-true value: the block
     // boundaries keep the compiler from moving each plane's setup code across planes (which
     // would keep all of it alive at once).
@@ -813,14 +832,15 @@ __device__ __forceinline__ void grad_shift_tile(
                 qm[z % kAhead] = fetch_mask(q[z % kAhead]);
             }
             const float4 s = sample(z, cur);
+            if (kKeep > 0 && z >= MAXD - kKeep) Sk[z >= MAXD - kKeep ? z - (MAXD - kKeep) : 0] = s;
             if (z < kTL)
                 s_T[z < kTL ? z : 0][tid] = T;
             else
                 Ts[z] = T;
             const float wgt = T * s.w;
-            c0 += wgt * s.x;
-            c1 += wgt * s.y;
-            c2 += wgt * s.z;
+            c0 = __builtin_fmaf(wgt, s.x, c0);
+            c1 = __builtin_fmaf(wgt, s.y, c1);
+            c2 = __builtin_fmaf(wgt, s.z, c2);
             T *= 1.0f - s.w;
             // (a cell outside the plane has a zero mask word; without a mask, check the range)
             const bool cell = owner && z < D && (MASKED || ((cur.row & 1u) && cur.off(xs) < (unsigned)rowbytes));
@@ -865,7 +885,7 @@ __device__ __forceinline__ void grad_shift_tile(
             const float d0 = c0 - images[3 * pix + 0];
             const float d1 = c1 - images[3 * pix + 1];
             const float d2 = c2 - images[3 * pix + 2];
-            if (owner) sq = d0 * d0 + d1 * d1 + d2 * d2;
+            if (owner) sq = __builtin_fmaf(d2, d2, __builtin_fmaf(d1, d1, d0 * d0));
             g0 = d0 * inv_n;
             g1 = d1 * inv_n;
             g2 = d2 * inv_n;
@@ -884,21 +904,32 @@ __device__ __forceinline__ void grad_shift_tile(
     asm volatile("" : "+s"(HW2), "+v"(lrow), "+v"(lcol));
     uint32_t rcode = 0;
     {
+        // (the first planes sampled are those below the kept ones: their loads run while the
+        // kept planes are processed)
         Taps2 q[kAhead];
 #pragma unroll
         for (int i = 0; i < kAhead; ++i)
-            if (i < MAXD) q[i] = fetch(MAXD - 1 - i, HW2);
+            if (i + kKeep < MAXD) q[i] = fetch(MAXD - 1 - kKeep - i, HW2);
 #pragma unroll
         for (int zz = 0; zz < MAXD; ++zz) {
             const int z = MAXD - 1 - zz;
             asm volatile("" : "+v"(go));
             if (!__builtin_amdgcn_readfirstlane(go)) break;
-            const Taps2 cur = q[zz % kAhead];
-            if (zz + kAhead < MAXD) q[zz % kAhead] = fetch(z - kAhead, HW2);
+            Taps2 cur;
+            float4 s;
+            if (zz < kKeep) {
+                cur.row = (unsigned)rl(lrow, z);
+                cur.col = (unsigned)rl(lcol, z);
+                s = Sk[zz < kKeep ? kKeep - 1 - zz : 0];
+            } else {
+                const int zk = zz - kKeep;
+                cur = q[zk % kAhead];
+                if (zz + kAhead < MAXD) q[zk % kAhead] = fetch(z - kAhead, HW2);
+                s = sample(z, cur);
+            }
             const float2 fr = s_f[z];
             const float fx = fr.x, fy = fr.y;
             if ((z & 3) == 3 || z == MAXD - 1) rcode = s_code[z >> 2][tid];
-            const float4 s = sample(z, cur);
             float4* buf = s_h[z & 1];
             // the colour of plane z against the composite behind it: the alpha adjoint's
             // factor and the step of the behind composite, B <- B + a (c - B)
@@ -910,7 +941,7 @@ __device__ __forceinline__ void grad_shift_tile(
                 a.x = g0 * ca;
                 a.y = g1 * ca;
                 a.z = g2 * ca;
-                a.w = Tz * (g0 * d0 + g1 * d1 + g2 * d2);
+                a.w = Tz * __builtin_fmaf(g2, d2, __builtin_fmaf(g1, d1, g0 * d0));
                 // horizontal half of the transposed bilinear: this ray (1 - fx) and the
                 // ray to the left (fx) both touch the owned cell's row
                 const float gx = 1.0f - fx;
@@ -934,10 +965,10 @@ __device__ __forceinline__ void grad_shift_tile(
                     const float4 hu = buf[tid - 64];
                     const float gy = 1.0f - fy;
                     float4 c;
-                    c.x = h.x * gy + hu.x * fy;
-                    c.y = h.y * gy + hu.y * fy;
-                    c.z = h.z * gy + hu.z * fy;
-                    c.w = h.w * gy + hu.w * fy;
+                    c.x = __builtin_fmaf(hu.x, fy, h.x * gy);
+                    c.y = __builtin_fmaf(hu.y, fy, h.y * gy);
+                    c.z = __builtin_fmaf(hu.z, fy, h.z * gy);
+                    c.w = __builtin_fmaf(hu.w, fy, h.w * gy);
                     // slot (rank, cell): the cell's byte offset in an FP32 RGBA plane is its
                     // tap offsets scaled from the storage's voxel size to 16 bytes
                     const unsigned cell16 = ((cur.row & ~7u) + cur.off(xs)) * (unsigned)(16 / S);
@@ -958,10 +989,10 @@ __device__ __forceinline__ void grad_shift_tile(
     }
 }
 
-// Up to 32 planes the kernel is held to 6 waves per SIMD (3 workgroups per CU), within
-// 80 registers and without spills (the first planes' transmittance is kept in LDS).
+// Waves per SIMD as grad_shift_waves gives them, without spills (the first planes'
+// transmittance is kept in LDS).
 template <int DT, int MAXD, bool MASKED>
-__global__ __launch_bounds__(kSX * kSY) __attribute__((amdgpu_waves_per_eu(MAXD <= 32 ? 6 : 1))) void k_grad_shift(
+__global__ __launch_bounds__(kSX * kSY) __attribute__((amdgpu_waves_per_eu(grad_shift_waves<DT, MAXD>()))) void k_grad_shift(
     const void* __restrict__ mpi, int D, int H, int W, int N, const hsgd_warp* __restrict__ warps,
     const float* __restrict__ images, const float* __restrict__ dimg, const uint64_t* __restrict__ mask,
     int kcap, float inv_n, float4* __restrict__ slots, float* __restrict__ partials, int ntx) {
@@ -1045,9 +1076,9 @@ __global__ __launch_bounds__(kSX * kSY) void k_render_shift(const void* __restri
             s.z = lerp_taps(f.t00.z, f.t01.z, wt);
             s.w = lerp_taps(f.t00.w, f.t01.w, wt);
             const float wgt = T * s.w;
-            c0 += wgt * s.x;
-            c1 += wgt * s.y;
-            c2 += wgt * s.z;
+            c0 = __builtin_fmaf(wgt, s.x, c0);
+            c1 = __builtin_fmaf(wgt, s.y, c1);
+            c2 = __builtin_fmaf(wgt, s.z, c2);
             T *= 1.0f - s.w;
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -1066,7 +1097,7 @@ __global__ __launch_bounds__(kSX * kSY) void k_render_shift(const void* __restri
             const float d0 = c0 - images[3 * pix + 0];
             const float d1 = c1 - images[3 * pix + 1];
             const float d2 = c2 - images[3 * pix + 2];
-            sq = d0 * d0 + d1 * d1 + d2 * d2;
+            sq = __builtin_fmaf(d2, d2, __builtin_fmaf(d1, d1, d0 * d0));
         }
     }
     if (partials) {
@@ -1172,14 +1203,14 @@ __device__ __forceinline__ void update_block(void* __restrict__ mpi, int D, int 
             // sparsity prior: d/da log(1.5 - |0.5 - a|) = sign(0.5 - a) / (1.5 - |0.5 - a|)
             const float d = 0.5f - v.w;
             const float sg = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
-            g.w += prior * (sg / (1.5f - fabsf(d)));
+            g.w = __builtin_fmaf(prior, sg / (1.5f - fabsf(d)), g.w);
         }
         if (grad_out) grad_out[(size_t)z * HW + p] = g;
         if (do_update) {
-            v.x = fminf(fmaxf(v.x - lr_rgb * g.x, 0.0f), 1.0f);
-            v.y = fminf(fmaxf(v.y - lr_rgb * g.y, 0.0f), 1.0f);
-            v.z = fminf(fmaxf(v.z - lr_rgb * g.z, 0.0f), 1.0f);
-            v.w = fminf(fmaxf(v.w - lr_a * g.w, 0.0f), 1.0f);
+            v.x = fminf(fmaxf(__builtin_fmaf(-lr_rgb, g.x, v.x), 0.0f), 1.0f);
+            v.y = fminf(fmaxf(__builtin_fmaf(-lr_rgb, g.y, v.y), 0.0f), 1.0f);
+            v.z = fminf(fmaxf(__builtin_fmaf(-lr_rgb, g.z, v.z), 0.0f), 1.0f);
+            v.w = fminf(fmaxf(__builtin_fmaf(-lr_a, g.w, v.w), 0.0f), 1.0f);
             Vox<DT>::store(mpi, z * HW + p, v);
         }
     }
@@ -1223,12 +1254,10 @@ __device__ __forceinline__ UpW up_weights(float fx, float fy) {
 // expression every upsampling path evaluates, so that they agree bit for bit.
 __device__ __forceinline__ float4 up_blend(const UpW& w, const float4& a, const float4& b, const float4& c,
                                            const float4& d) {
-    float4 o;
-    o.x = w.w00 * a.x + w.w10 * b.x + w.w01 * c.x + w.w11 * d.x;
-    o.y = w.w00 * a.y + w.w10 * b.y + w.w01 * c.y + w.w11 * d.y;
-    o.z = w.w00 * a.z + w.w10 * b.z + w.w01 * c.z + w.w11 * d.z;
-    o.w = w.w00 * a.w + w.w10 * b.w + w.w01 * c.w + w.w11 * d.w;
-    return o;
+    auto f = [&](float a_, float b_, float c_, float d_) {
+        return __builtin_fmaf(w.w11, d_, __builtin_fmaf(w.w01, c_, __builtin_fmaf(w.w10, b_, w.w00 * a_)));
+    };
+    return make_float4(f(a.x, b.x, c.x, d.x), f(a.y, b.y, c.y, d.y), f(a.z, b.z, c.z, d.z), f(a.w, b.w, c.w, d.w));
 }
 
 // The four source taps of output voxel i of plane z of the 2x upsampling of a [D][h][w]
@@ -1615,9 +1644,12 @@ __global__ __launch_bounds__(256) void k_batch_select(const BatchTable* __restri
 }
 
 // Tiles are taken in the XCD-grouped order of the flat item list (the grid is a multiple
-// of 8 workgroups), so neighbouring tiles of one request share an XCD's L2.
+// of 8 workgroups), so neighbouring tiles of one request share an XCD's L2. Register
+// budget as for k_grad_shift where the tile keeps samples.
 template <int DT, int MAXD>
-__global__ __launch_bounds__(kSX * kSY) void k_batch_grad(const BatchTable* __restrict__ t, int kk) {
+__global__ __launch_bounds__(kSX * kSY) __attribute__((amdgpu_waves_per_eu(
+    grad_shift_keep<DT, MAXD>() > 0 ? grad_shift_waves<DT, MAXD>() : 1))) void k_batch_grad(const BatchTable* __restrict__ t,
+                                                                                          int kk) {
     const int total = t->total[kk];
     for (int i = blockIdx.x; i < total; i += gridDim.x) {
         const int g = xcd_tile(i, total);
@@ -1628,7 +1660,9 @@ __global__ __launch_bounds__(kSX * kSY) void k_batch_grad(const BatchTable* __re
         // kept live across tiles
         unsigned tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
-        grad_shift_tile<DT, MAXD, true>(b.mpi, b.D, b.H, b.W, b.N, b.warps, b.images, nullptr, b.mask, b.kcap,
+        // (the persistent loop's own state leaves room for 8 kept planes; the results do
+        // not depend on how many are kept)
+        grad_shift_tile<DT, MAXD, true, (grad_shift_keep<DT, MAXD>() > 0 ? 8 : 0)>(b.mpi, b.D, b.H, b.W, b.N, b.warps, b.images, nullptr, b.mask, b.kcap,
                                         1.0f / (float)b.N, b.slots, b.partials, b.ntx,
                                         g - t->pre[kk][sl], tid);
     }
