@@ -152,6 +152,7 @@ GRAD_CASES = [
     (21, 3, 13, 131, 45, 50.0, 0.1, False, GRAD_RTOL),
     (22, 2, 64, 40, 20, 30.0, 0.1, False, GRAD_RTOL),
     (23, 4, 32, 160, 120, 128.0, 0.1, False, GRAD_RTOL),
+    (25, 3, 27, 100, 70, 80.0, 0.1, False, GRAD_RTOL),       # 27 of 32 planes: transparent kept planes
     (24, 3, 9, 70, 52, 60.0, 0.1, True, GRAD_RTOL),           # rotation + z translation
 ]
 
@@ -188,11 +189,12 @@ def test_sparse_gradient_is_masked_dense_gradient(case):
     grad_close(g[S], g_ref[S], rtol, f"restricted seed {seed}")
 
 
-@pytest.mark.parametrize("general", [False, True], ids=["shift", "general"])
-def test_bf16_storage_gradient_matches_oracle(general):
+@pytest.mark.parametrize("general,D", [(False, 12), (True, 12), (False, 27)],
+                         ids=["shift", "general", "shift_D27"])
+def test_bf16_storage_gradient_matches_oracle(general, D):
     """BF16 storage with FP32 arithmetic in the gradient kernels (translation and general
     warps): the oracle's FP64 gradient of the BF16-rounded MPI, dense and restricted."""
-    seed, N, D, W, H = 26, 3, 12, 90, 50
+    seed, N, W, H = 26, 3, 90, 50
     rg, M, I = problem(seed, N, D, W, H, 60.0, 0.1, general, lo=0.05, hi=0.95)
     Mq = bf16_vals(M)
     L_ref, g_ref = O.loss_and_grad(Mq, oracle_maps(O, rg), I)

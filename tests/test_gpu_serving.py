@@ -208,6 +208,27 @@ def test_steps_on_alternating_streams_equal_refine(mix):
     assert torch.equal(st.loss_log[:sum(sc.iters)], ref_loss)
 
 
+def test_fp32_request_equals_refine(mix):
+    """FP32 storage through the batch core: a 512x384x32 request equals hsgd_refine in FP32,
+    bitwise. (The batched gradient kernel keeps the samples of fewer planes between its two
+    scans than the single-request one; the results must not depend on that.)"""
+    si = mix[2]
+    sc = si.sc
+    assert (sc.W, sc.H, sc.D) == (512, 384, 32)
+    st = serving.new_stream(0, si, dtype=torch.float32)
+    st.levels[0].copy_(si.inits32[1])
+    torch.cuda.synchronize()
+    b = hsgd.Batch(1, sc.D, sc.N, sc.H, sc.W, sc.k, dtype=torch.float32)
+    assert b.admit(st) is not None
+    while b.step()[0]:
+        pass
+    torch.cuda.synchronize()
+    ref, ref_loss = alone(si, 1, torch.float32)
+    assert st.result.dtype == torch.float32
+    assert torch.equal(st.result, ref)
+    assert torch.equal(st.loss_log[:sum(sc.iters)], ref_loss)
+
+
 def test_served_requests_match_oracle_bf16_refine():
     """Two requests of different frame sizes and plane counts (256x192x16, k 2 and
     512x384x32, k 4) served together in one batch, each against the oracle's BF16 refine
