@@ -695,7 +695,8 @@ __device__ __forceinline__ void grad_shift_tile(
     // the front-to-back scan to the end of the back-to-front one), so at 6 waves per SIMD
     // they go to LDS instead of registers, which would otherwise spill to scratch memory
     // (whose reloads wait for every load in flight, the look-ahead included). Six planes
-    // keep 32 planes within 80 registers; with 49.5 KB of LDS three workgroups fit a CU.
+    // keep 32 planes within 80 registers at 6 waves per SIMD; with 49.5 KB of LDS three
+    // workgroups fit a CU (two in the 4-wave form that keeps samples).
     constexpr int kTL = MAXD <= 32 ? 6 : 0;
     __shared__ float s_T[kTL > 0 ? kTL : 1][kSX * kSY];
     const int view = tile % N;
@@ -748,8 +749,9 @@ __device__ __forceinline__ void grad_shift_tile(
     // transparent plane) and select nothing. The taps of plane z +- kAhead are loaded while
     // plane z is processed (see the end of each scan), and a scheduling fence per plane
     // keeps that look-ahead (and the register footprint) fixed. The second scan samples the
-    // planes again instead of keeping them in registers: that keeps the kernel small enough
-    // for several workgroups per CU, which hides the per-plane barrier.
+    // planes again (all but the last kKeep, below) instead of keeping them in registers: that
+    // keeps the kernel small enough for several workgroups per CU, which hides the per-plane
+    // barrier.
     struct Taps2 {
         typename Vox<DT>::Raw t00, t01;   // taps of rows y0 and y0 + 1, as stored (right-hand taps come from lane + 1)
         unsigned row;      // in-plane byte offset of the upper tap row, with lrow's flags
