@@ -205,8 +205,12 @@ hsgd_status refine_run(const char* fn, hsgd_mpi* levels, const hsgd_views* views
     const int N = views[0].N;
     const RefineWs R = refine_ws(top.D, top.H, top.W, N, sel.k, L);
 
+    // one mask and one workspace region sized for the finest level serve every level
+    uint64_t* mask = reinterpret_cast<uint64_t*>((char*)ws + R.mask_off);
     // target pyramid: coarser images that were not given are box means of the finer ones,
-    // up to three consecutive missing levels from one launch
+    // up to three consecutive missing levels from one launch; the first such launch also
+    // makes the coarsest level's first selection when that level iterates
+    bool first_selected = false;
     const float* img[16];
     img[L - 1] = views[L - 1].images;
     for (int l = L - 2; l >= 0;) {
@@ -221,13 +225,18 @@ hsgd_status refine_run(const char* fn, hsgd_mpi* levels, const hsgd_views* views
             dst[nl] = reinterpret_cast<float*>((char*)ws + R.pyr_off[l - nl]);
             ++nl;
         }
-        int e = launch_pyramid(img[l + 1], N, levels[l + 1].H, levels[l + 1].W, nl, dst, stream);
+        int e;
+        if (!first_selected && iters[0] > 0) {
+            e = launch_select_pyramid(levels[0], sel.k, sel.tau, sel.rule, mask, img[l + 1], N, levels[l + 1].H,
+                                      levels[l + 1].W, nl, dst, stream);
+            first_selected = true;
+        } else {
+            e = launch_pyramid(img[l + 1], N, levels[l + 1].H, levels[l + 1].W, nl, dst, stream);
+        }
         if (e) return hip_status(e, fn);
         for (int j = 0; j < nl; ++j) img[l - j] = dst[j];
         l -= nl;
     }
-    // one mask and one workspace region sized for the finest level serve every level
-    uint64_t* mask = reinterpret_cast<uint64_t*>((char*)ws + R.mask_off);
     char* inner = (char*)ws + R.inner_off;
     int it_global = 0;
     for (int l = 0; l < L; ++l) {
@@ -244,7 +253,8 @@ hsgd_status refine_run(const char* fn, hsgd_mpi* levels, const hsgd_views* views
         float4* slots = reinterpret_cast<float4*>(inner + G.slots_off);
         float* partials = reinterpret_cast<float*>(inner + G.partial_off);
         for (int it = 0; it < iters[l]; ++it, ++it_global) {
-            int e = (fused && it == 0) ? 0 : launch_select(levels[l], sel.k, sel.tau, sel.rule, mask, nullptr, nullptr, stream);
+            const bool selected = (fused || (l == 0 && first_selected)) && it == 0;
+            int e = selected ? 0 : launch_select(levels[l], sel.k, sel.tau, sel.rule, mask, nullptr, nullptr, stream);
             if (e) return hip_status(e, fn);
             e = launch_grad_step(levels[l], v, mask, sel.k, nullptr, lr_rgb, lr_alpha, lambda_s, nullptr,
                                  loss_log ? loss_log + it_global : nullptr, slots, partials, stream);

@@ -133,6 +133,9 @@ int launch_upsample_select(const hsgd_mpi& coarse, const hsgd_mpi& fine, int k, 
 // nl (1..3) successive 2x2 box means of [N][H][W][3] images in one launch: out[j] receives
 // level j + 1 below the input (H and W multiples of 2^nl).
 int launch_pyramid(const float* img, int N, int H, int W, int nl, float* const* out, hipStream_t s);
+// launch_pyramid and launch_select (mask only, no id list) of an independent level in one launch.
+int launch_select_pyramid(const hsgd_mpi& m, int k, float tau, int rule, uint64_t* mask, const float* img, int N,
+                          int H, int W, int nl, float* const* out, hipStream_t s);
 int launch_downsample(const float* img, int N, int H, int W, float* out, hipStream_t s);
 // plane-sweep volume levels 0..L-1 ([N][D][H>>l][W>>l][3] FP32 or BF16; out[l] NULL: not stored)
 constexpr int kPsvMaxL = 5;

@@ -1533,13 +1533,11 @@ __device__ __forceinline__ void downsample_pixel(const float* __restrict__ img, 
 // and writes its share of every level (out[j]: level j + 1), each level the box means of
 // the one above as downsample_pixel computes them.
 template <int NL>
-__global__ __launch_bounds__(256) void k_pyramid(const float* __restrict__ img, int H, int W,
-                                                 float* __restrict__ out0, float* __restrict__ out1,
-                                                 float* __restrict__ out2) {
+__device__ __forceinline__ void pyramid_block(const float* __restrict__ img, int H, int W, float* __restrict__ out0,
+                                              float* __restrict__ out1, float* __restrict__ out2, int n, int bx) {
     constexpr int S = 1 << NL;
-    const int n = blockIdx.y;
     const int hc = H >> NL, wc = W >> NL;
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int i = bx * 256 + threadIdx.x;
     if (i >= hc * wc) return;
     const int x = i % wc, y = i / wc;
     float cur[S / 2][S / 2][3];
@@ -1576,6 +1574,32 @@ __global__ __launch_bounds__(256) void k_pyramid(const float* __restrict__ img, 
                         cur[r][c][ch] = box4(cur[2 * r][2 * c][ch], cur[2 * r][2 * c + 1][ch],
                                              cur[2 * r + 1][2 * c][ch], cur[2 * r + 1][2 * c + 1][ch]);
         }
+    }
+}
+
+template <int NL>
+__global__ __launch_bounds__(256) void k_pyramid(const float* __restrict__ img, int H, int W,
+                                                 float* __restrict__ out0, float* __restrict__ out1,
+                                                 float* __restrict__ out2) {
+    pyramid_block<NL>(img, H, W, out0, out1, out2, blockIdx.y, blockIdx.x);
+}
+
+// The first selection of the coarsest level and the target pyramid are independent: one
+// launch runs both, its first nsel blocks selecting (as k_select) and the others reducing
+// (as k_pyramid, block b of view n at nsel + n * nbx + b), so neither waits for the other.
+template <int DT, int MAXD, int NL>
+__global__ __launch_bounds__(256) void k_select_pyramid(const void* __restrict__ mpi, int D, int HW, int k,
+                                                        float tau, int rule, uint64_t* __restrict__ mask,
+                                                        int nsel, const float* __restrict__ img, int H, int W,
+                                                        float* __restrict__ out0, float* __restrict__ out1,
+                                                        float* __restrict__ out2, int nbx) {
+    const int b = blockIdx.x;
+    if (b < nsel) {
+        const int p = b * 256 + threadIdx.x;
+        if (p < HW) mask[p] = select_bits<DT, MAXD>(mpi, D, HW, p, k, tau, rule);
+    } else {
+        const int j = b - nsel;
+        pyramid_block<NL>(img, H, W, out0, out1, out2, j / nbx, j % nbx);
     }
 }
 
@@ -1863,6 +1887,27 @@ int launch_pyramid(const float* img, int N, int H, int W, int nl, float* const* 
         hipLaunchKernelGGL(k_pyramid<2>, grid, dim3(256), 0, s, img, H, W, out[0], out[1], nullptr);
     else
         hipLaunchKernelGGL(k_pyramid<3>, grid, dim3(256), 0, s, img, H, W, out[0], out[1], out[2]);
+    return (int)hipGetLastError();
+}
+
+int launch_select_pyramid(const hsgd_mpi& m, int k, float tau, int rule, uint64_t* mask, const float* img, int N,
+                          int H, int W, int nl, float* const* out, hipStream_t s) {
+    const int HW = m.H * m.W;
+    const int nsel = (int)ceil_div(HW, 256);
+    const int nbx = (int)ceil_div((int64_t)(H >> nl) * (W >> nl), 256);
+    const dim3 grid((unsigned)(nsel + nbx * N));
+    ProfScope ps(HSGD_K_SELECT, s);
+    HSGD_DISPATCH_T(m.dtype, HSGD_DISPATCH_D(m.D, {
+        if (nl == 1)
+            hipLaunchKernelGGL((k_select_pyramid<DT, MD, 1>), grid, dim3(256), 0, s, m.rgba, m.D, HW, k, tau, rule,
+                               mask, nsel, img, H, W, out[0], nullptr, nullptr, nbx);
+        else if (nl == 2)
+            hipLaunchKernelGGL((k_select_pyramid<DT, MD, 2>), grid, dim3(256), 0, s, m.rgba, m.D, HW, k, tau, rule,
+                               mask, nsel, img, H, W, out[0], out[1], nullptr, nbx);
+        else
+            hipLaunchKernelGGL((k_select_pyramid<DT, MD, 3>), grid, dim3(256), 0, s, m.rgba, m.D, HW, k, tau, rule,
+                               mask, nsel, img, H, W, out[0], out[1], out[2], nbx);
+    }));
     return (int)hipGetLastError();
 }
 
