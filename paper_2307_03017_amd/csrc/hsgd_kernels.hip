@@ -859,14 +859,10 @@ __device__ __forceinline__ void grad_shift_tile(
             __builtin_amdgcn_sched_barrier(0);
         }
         // The look-ahead loads are consumed on the path out of the loop as well, so that
-        // each is issued before its plane's branch rather than sunk to its use two planes
-        // later. Up to 32 planes that hides the load latency; with 64 planes (4 waves per
-        // SIMD with or without it) it measured slower, so there the loads sink to their use.
-        if constexpr (MAXD <= 32) {
+        // each is issued before its plane's branch rather than sunk to its use planes later.
 #pragma unroll
-            for (int i = 0; i < kAhead; ++i)
-                asm volatile("" ::"v"(q[i].t00.x), "v"(q[i].t01.x), "v"((uint32_t)qm[i]));
-        }
+        for (int i = 0; i < kAhead; ++i)
+            asm volatile("" ::"v"(q[i].t00.x), "v"(q[i].t01.x), "v"((uint32_t)qm[i]));
     }
     // planes where the wave below has selected cells: it needs this wave's adjoints
     if (lane == 0) s_bits[wv] = own_bits;
@@ -980,10 +976,9 @@ __device__ __forceinline__ void grad_shift_tile(
             }
             __builtin_amdgcn_sched_barrier(0);
         }
-        if constexpr (MAXD <= 32) {
 #pragma unroll
-            for (int i = 0; i < kAhead; ++i) asm volatile("" ::"v"(q[i].t00.x), "v"(q[i].t01.x));
-        }
+        for (int i = 0; i < kAhead; ++i)
+            if (i + kKeep < MAXD) asm volatile("" ::"v"(q[i].t00.x), "v"(q[i].t01.x));
     }
     if (partials) {
         const float tot = block_sum(sq, sred);
