@@ -668,15 +668,22 @@ __device__ __forceinline__ float lerp_taps(float a0, float a1, const float4& wt)
 // Planes whose front-to-back samples the gradient tile keeps for its back-to-front scan,
 // and the waves per SIMD the kernel is compiled for: up to 32 planes 6 (3 workgroups per CU,
 // within 80 registers), except FP32 at 32 planes, which keeps the samples of its last 12
-// planes in the registers of 4 waves per SIMD (2 workgroups per CU) and measured faster;
-// 64 planes run at 4 waves per SIMD without a register bound.
+// planes in the registers of 4 waves per SIMD (2 workgroups per CU) and measured faster.
+// 64 planes run at 4 waves per SIMD (their LDS allows 2 workgroups per CU); BF16 there
+// keeps 4 planes within that register budget.
 template <int DT, int MAXD>
 constexpr int grad_shift_keep() {
-    return DT == HSGD_FP32 && MAXD == 32 ? 12 : 0;
+    return DT == HSGD_FP32 && MAXD == 32 ? 12 : (DT == HSGD_BF16 && MAXD == 64 ? 4 : 0);
 }
 template <int DT, int MAXD>
 constexpr int grad_shift_waves() {
-    return MAXD > 32 ? 1 : (grad_shift_keep<DT, MAXD>() > 0 ? 4 : 6);
+    return grad_shift_keep<DT, MAXD>() > 0 ? 4 : (MAXD > 32 ? 1 : 6);
+}
+// The batched kernel's persistent loop needs registers of its own: it keeps 8 planes at FP32
+// and 32 planes, none elsewhere (the results do not depend on how many are kept).
+template <int DT, int MAXD>
+constexpr int batch_grad_keep() {
+    return DT == HSGD_FP32 && MAXD == 32 ? 8 : 0;
 }
 
 template <int DT, int MAXD, bool MASKED, int KEEP = grad_shift_keep<DT, MAXD>()>
@@ -1669,7 +1676,7 @@ __global__ __launch_bounds__(256) void k_batch_select(const BatchTable* __restri
 // budget as for k_grad_shift where the tile keeps samples.
 template <int DT, int MAXD>
 __global__ __launch_bounds__(kSX * kSY) __attribute__((amdgpu_waves_per_eu(
-    grad_shift_keep<DT, MAXD>() > 0 ? grad_shift_waves<DT, MAXD>() : 1))) void k_batch_grad(const BatchTable* __restrict__ t,
+    batch_grad_keep<DT, MAXD>() > 0 ? grad_shift_waves<DT, MAXD>() : 1))) void k_batch_grad(const BatchTable* __restrict__ t,
                                                                                           int kk) {
     const int total = t->total[kk];
     for (int i = blockIdx.x; i < total; i += gridDim.x) {
@@ -1681,9 +1688,7 @@ __global__ __launch_bounds__(kSX * kSY) __attribute__((amdgpu_waves_per_eu(
         // kept live across tiles
         unsigned tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
-        // (the persistent loop's own state leaves room for 8 kept planes; the results do
-        // not depend on how many are kept)
-        grad_shift_tile<DT, MAXD, true, (grad_shift_keep<DT, MAXD>() > 0 ? 8 : 0)>(b.mpi, b.D, b.H, b.W, b.N, b.warps, b.images, nullptr, b.mask, b.kcap,
+        grad_shift_tile<DT, MAXD, true, batch_grad_keep<DT, MAXD>()>(b.mpi, b.D, b.H, b.W, b.N, b.warps, b.images, nullptr, b.mask, b.kcap,
                                         1.0f / (float)b.N, b.slots, b.partials, b.ntx,
                                         g - t->pre[kk][sl], tid);
     }

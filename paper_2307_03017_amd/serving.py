@@ -45,9 +45,9 @@ def make_mix(mix_seed: int = 7, variants: int = 4, device="cuda", dtype=torch.bf
     rng = np.random.default_rng(mix_seed)
     mix = MIX if mix is None else mix
     out = []
-    for cfg, seed in mix:
+    for cfg, seed, *over in mix:                # (name, seed[, scene overrides])
         N = int(rng.integers(3, 6))
-        sc = scenes.make_scene(cfg, seed=seed, N=N)
+        sc = scenes.make_scene(cfg, seed=seed, N=N, **(over[0] if over else {}))
         table = hsgd.level_warps(sc.K_ref(), sc.K_views(), sc.R_views(), sc.t_views(), sc.depths,
                                  sc.W, sc.H, sc.W, sc.H, device)
         gt = torch.from_numpy(sc.gt_mpi(np.float32)).to(device)

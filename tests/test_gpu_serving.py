@@ -229,6 +229,26 @@ def test_fp32_request_equals_refine(mix):
     assert torch.equal(st.loss_log[:sum(sc.iters)], ref_loss)
 
 
+def test_bf16_64_plane_request_equals_refine():
+    """A 256x192 request with 64 planes (BF16) through the batch core equals hsgd_refine,
+    bitwise (at 64 planes the single-request gradient kernel keeps samples between its two
+    scans and the batched one does not)."""
+    si = serving.make_mix(variants=1, mix=[("s256", 110, dict(D=64))])[0]
+    sc = si.sc
+    assert sc.D == 64
+    st = serving.new_stream(0, si)
+    st.levels[0].copy_(si.inits[0])
+    torch.cuda.synchronize()
+    b = hsgd.Batch(1, sc.D, sc.N, sc.H, sc.W, sc.k)
+    assert b.admit(st) is not None
+    while b.step()[0]:
+        pass
+    torch.cuda.synchronize()
+    ref, ref_loss = alone(si, 0, torch.bfloat16)
+    assert torch.equal(st.result, ref)
+    assert torch.equal(st.loss_log[:sum(sc.iters)], ref_loss)
+
+
 def test_served_requests_match_oracle_bf16_refine():
     """Two requests of different frame sizes and plane counts (256x192x16, k 2 and
     512x384x32, k 4) served together in one batch, each against the oracle's BF16 refine
