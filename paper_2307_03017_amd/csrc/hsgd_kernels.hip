@@ -120,18 +120,26 @@ struct Vox<HSGD_BF16> {
     }
 };
 
+// The four taps of a sample, loaded, and their bilinear blend (explicit FMAs: every scan
+// that samples a plane gets the same bits).
+struct Tap4 {
+    float4 a, b, c, d;
+};
+template <int DT>
+__device__ __forceinline__ Tap4 load_taps(const void* mpi, int plane_base, const Taps& t) {
+    return Tap4{Vox<DT>::load(mpi, plane_base + t.i00), Vox<DT>::load(mpi, plane_base + t.i10),
+                Vox<DT>::load(mpi, plane_base + t.i01), Vox<DT>::load(mpi, plane_base + t.i11)};
+}
+__device__ __forceinline__ float4 blend_taps(const Taps& t, const Tap4& v) {
+    auto f = [&](float a, float b, float c, float d) {
+        return __builtin_fmaf(t.w11, d, __builtin_fmaf(t.w01, c, __builtin_fmaf(t.w10, b, t.w00 * a)));
+    };
+    return make_float4(f(v.a.x, v.b.x, v.c.x, v.d.x), f(v.a.y, v.b.y, v.c.y, v.d.y), f(v.a.z, v.b.z, v.c.z, v.d.z),
+                       f(v.a.w, v.b.w, v.c.w, v.d.w));
+}
 template <int DT>
 __device__ __forceinline__ float4 sample(const void* mpi, int plane_base, const Taps& t) {
-    const float4 a = Vox<DT>::load(mpi, plane_base + t.i00);
-    const float4 b = Vox<DT>::load(mpi, plane_base + t.i10);
-    const float4 c = Vox<DT>::load(mpi, plane_base + t.i01);
-    const float4 d = Vox<DT>::load(mpi, plane_base + t.i11);
-    float4 s;
-    s.x = t.w00 * a.x + t.w10 * b.x + t.w01 * c.x + t.w11 * d.x;
-    s.y = t.w00 * a.y + t.w10 * b.y + t.w01 * c.y + t.w11 * d.y;
-    s.z = t.w00 * a.z + t.w10 * b.z + t.w01 * c.z + t.w11 * d.z;
-    s.w = t.w00 * a.w + t.w10 * b.w + t.w01 * c.w + t.w11 * d.w;
-    return s;
+    return blend_taps(t, load_taps<DT>(mpi, plane_base, t));
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -667,13 +675,13 @@ __device__ __forceinline__ float lerp_taps(float a0, float a1, const float4& wt)
 // workgroup calls it.
 // Planes whose front-to-back samples the gradient tile keeps for its back-to-front scan,
 // and the waves per SIMD the kernel is compiled for: up to 32 planes 6 (3 workgroups per CU,
-// within 80 registers), except FP32 at 32 planes, which keeps the samples of its last 12
+// within 80 registers), except FP32 at 32 planes, which keeps the samples of its last 16
 // planes in the registers of 4 waves per SIMD (2 workgroups per CU) and measured faster.
 // 64 planes run at 4 waves per SIMD (their LDS allows 2 workgroups per CU); BF16 there
 // keeps 4 planes within that register budget.
 template <int DT, int MAXD>
 constexpr int grad_shift_keep() {
-    return DT == HSGD_FP32 && MAXD == 32 ? 12 : (DT == HSGD_BF16 && MAXD == 64 ? 4 : 0);
+    return DT == HSGD_FP32 && MAXD == 32 ? 16 : (DT == HSGD_BF16 && MAXD == 64 ? 4 : 0);
 }
 template <int DT, int MAXD>
 constexpr int grad_shift_waves() {
@@ -703,8 +711,10 @@ __device__ __forceinline__ void grad_shift_tile(
     // they go to LDS instead of registers, which would otherwise spill to scratch memory
     // (whose reloads wait for every load in flight, the look-ahead included). Six planes
     // keep 32 planes within 80 registers at 6 waves per SIMD; with 49.5 KB of LDS three
-    // workgroups fit a CU (two in the 4-wave form that keeps samples).
-    constexpr int kTL = MAXD <= 32 ? 6 : 0;
+    // workgroups fit a CU. The 4-wave form that keeps 16 planes' samples has 80 KB per
+    // workgroup (two per CU): 18 planes of transmittance there (74 KB) make the registers
+    // for the kept samples.
+    constexpr int kTL = MAXD <= 32 ? (KEEP > 8 ? 18 : 6) : 0;
     __shared__ float s_T[kTL > 0 ? kTL : 1][kSX * kSY];
     const int view = tile % N;
     const int t2 = tile / N;
