@@ -153,6 +153,7 @@ GRAD_CASES = [
     (22, 2, 64, 40, 20, 30.0, 0.1, False, GRAD_RTOL),
     (23, 4, 32, 160, 120, 128.0, 0.1, False, GRAD_RTOL),
     (25, 3, 27, 100, 70, 80.0, 0.1, False, GRAD_RTOL),       # 27 of 32 planes: transparent kept planes
+    (27, 2, 50, 60, 40, 50.0, 0.1, False, GRAD_RTOL),        # 50 of 64 planes
     (24, 3, 9, 70, 52, 60.0, 0.1, True, GRAD_RTOL),           # rotation + z translation
 ]
 
@@ -189,8 +190,8 @@ def test_sparse_gradient_is_masked_dense_gradient(case):
     grad_close(g[S], g_ref[S], rtol, f"restricted seed {seed}")
 
 
-@pytest.mark.parametrize("general,D", [(False, 12), (True, 12), (False, 27)],
-                         ids=["shift", "general", "shift_D27"])
+@pytest.mark.parametrize("general,D", [(False, 12), (True, 12), (False, 27), (False, 50)],
+                         ids=["shift", "general", "shift_D27", "shift_D50"])
 def test_bf16_storage_gradient_matches_oracle(general, D):
     """BF16 storage with FP32 arithmetic in the gradient kernels (translation and general
     warps): the oracle's FP64 gradient of the BF16-rounded MPI, dense and restricted."""
