@@ -186,6 +186,16 @@ def test_level_transition_selects_like_select_active(D, k, rule, quant, dtype, W
     two-level refine that spends its only iteration on the finer level must equal, bit for
     bit, the upsampling, hsgd_select_active on the stored level and one hsgd_grad_step on
     that mask with the same rates (quantised alphas put exact ties into the scores)."""
+    _level_transition_case(D, k, rule, quant, dtype, W, H)
+
+
+@pytest.mark.parametrize("W, H", [(64, 32), (2048, 256)], ids=["per_pixel", "blocks"])
+def test_level_transition_with_threshold(W, H):
+    """The same with the score threshold tau on, through both level-transition kernels."""
+    _level_transition_case(16, 5, "topk", False, torch.float32, W, H, tau=0.02)
+
+
+def _level_transition_case(D, k, rule, quant, dtype, W, H, tau=-1.0):
     N, f = 3, 40.0
     rng = np.random.default_rng(80 + D)
     rg = shift_rig(W, H, D, f, rng.uniform(-0.05, 0.05, size=(N, 2)))
@@ -195,11 +205,14 @@ def test_level_transition_selects_like_select_active(D, k, rule, quant, dtype, W
     M0d = to_dev(M0, dtype)
     I = to_dev(rng.uniform(size=(N, H, W, 3)))
     lr_rgb, lr_a = 0.7, 0.9
-    print(f"level transition D={D} k={k} rule={rule} {dtype} {W}x{H}", flush=True)
+    print(f"level transition D={D} k={k} rule={rule} tau={tau} {dtype} {W}x{H}", flush=True)
     out, losses = hsgd.hsgd_refine(M0d, I, rg["K_ref"], rg["K"], rg["R"], rg["t"], rg["depths"], (0, 1), k,
-                                   lr_rgb=lr_rgb, lr_alpha=lr_a, rule=rule)
+                                   tau=tau, lr_rgb=lr_rgb, lr_alpha=lr_a, rule=rule)
     up = hsgd.hsgd_upsample2x(M0d)
-    mask = hsgd.hsgd_select_active(up, k, rule=rule, with_ids=False)
+    mask = hsgd.hsgd_select_active(up, k, tau=tau, rule=rule, with_ids=False)
+    if tau >= 0:                                   # the threshold drops some selected planes
+        S = mask_bits(mask.cpu().numpy(), D)
+        assert 0 < S.sum() < k * (H * W)
     _, loss = hsgd.hsgd_grad_step(up, device_warps(hsgd, rg), N, images=I, mask=mask, kcap=k, lr_rgb=lr_rgb,
                                   lr_alpha=lr_a, want_loss=True)
     torch.cuda.synchronize()
